@@ -1,0 +1,118 @@
+"""Residual network f_D and its Jacobian J_D in float64 -- TEST INFRASTRUCTURE.
+
+The learned part of the model partition f = f_F + f_D (Sec. III, eq. (1);
+full residual model eq. (7)) is a multilayer perceptron
+
+    z_0 = [v, w, q, u]  (14 values, raw, in this order)
+    a_l = W_l h_{l-1} + b_l,  h_l = act(a_l),   l = 1..L      (h_0 = z_0)
+    y   = W_{L+1} h_L + b_{L+1}                  (6 values)
+
+with act = SiLU (a * logistic(a)) or identity.  Its output is placed in the
+state derivative as f_D = [0_3 (p), 0_4 (q), y_0..2 (v-dot, world frame),
+y_3..5 (w-dot, body frame)]; eq. (7) writes the two leading zero blocks as 0_2.
+
+J_D = dy/dz_0 = W_{L+1} diag(act'(a_L)) W_L ... diag(act'(a_1)) W_1 (6 x 14) is the
+chain rule written out; it is evaluated by reverse accumulation (6 outputs < 14
+inputs).  f_D-bar and J_D at a node are the parameters of the local
+approximation eq. (4) (Sec. IV-A).
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# z_0 index -> state index (columns of the state Jacobian the residual touches)
+Z_V = slice(0, 3)    # v  -> x[7:10]
+Z_W = slice(3, 6)    # w  -> x[10:13]
+Z_Q = slice(6, 10)   # q  -> x[3:7]
+Z_U = slice(10, 14)  # u
+Z_TO_X = np.array([7, 8, 9, 10, 11, 12, 3, 4, 5, 6])
+
+
+def pack_input(x: np.ndarray, u: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    return np.concatenate([x[:, 7:10], x[:, 10:13], x[:, 3:7], u], axis=1)
+
+
+def logistic(a):
+    return 1.0 / (1.0 + np.exp(-a))
+
+
+def silu(a):
+    return a * logistic(a)
+
+
+def silu_prime(a):
+    s = logistic(a)
+    return s * (1.0 + a * (1.0 - s))
+
+
+class MLP:
+    """Float64 view of a residual network.  ``Ws[l]`` is (fan_out, fan_in)."""
+
+    def __init__(self, Ws: Sequence[np.ndarray], bs: Sequence[np.ndarray], act: str = "silu"):
+        self.Ws = [np.asarray(W, dtype=np.float64) for W in Ws]
+        self.bs = [np.asarray(b, dtype=np.float64) for b in bs]
+        if act not in ("silu", "identity"):
+            raise ValueError(act)
+        self.act = act
+
+    @property
+    def n_hidden(self) -> int:
+        return len(self.Ws) - 1
+
+    def _act(self, a):
+        return silu(a) if self.act == "silu" else a
+
+    def _act_prime(self, a):
+        return silu_prime(a) if self.act == "silu" else np.ones_like(a)
+
+    def forward(self, z: np.ndarray, keep: bool = False):
+        """y (n, 6); with keep=True also the pre-activations a_1..a_L."""
+        h = np.asarray(z, dtype=np.float64)
+        pre = []
+        for W, b in zip(self.Ws[:-1], self.bs[:-1]):
+            a = h @ W.T + b
+            pre.append(a)
+            h = self._act(a)
+        y = h @ self.Ws[-1].T + self.bs[-1]
+        return (y, pre) if keep else y
+
+    def jacobian(self, z: np.ndarray):
+        """(y (n,6), J_D (n,6,14)) by reverse accumulation of the chain rule."""
+        y, pre = self.forward(z, keep=True)
+        n = y.shape[0]
+        G = np.broadcast_to(self.Ws[-1], (n,) + self.Ws[-1].shape)
+        for l in range(self.n_hidden - 1, -1, -1):
+            G = (G * self._act_prime(pre[l])[:, None, :]) @ self.Ws[l]
+        return y, np.ascontiguousarray(G)
+
+
+def residual_in_state(y: np.ndarray, J: np.ndarray):
+    """Scatter the network value/Jacobian into state coordinates (eq. (7)).
+
+    Returns f_bar (n,13), J_x (n,13,13), J_u (n,13,4)."""
+    n = y.shape[0]
+    f_bar = np.zeros((n, 13))
+    f_bar[:, 7:13] = y
+    J_x = np.zeros((n, 13, 13))
+    J_x[:, 7:13, Z_TO_X] = J[:, :, 0:10]
+    J_u = np.zeros((n, 13, 4))
+    J_u[:, 7:13, :] = J[:, :, 10:14]
+    return f_bar, J_x, J_u
+
+
+def residual_value(model: Optional[MLP], x: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """f_D(x, u) as a 13-vector field (zeros without a network)."""
+    n = x.shape[0]
+    out = np.zeros((n, 13), dtype=np.result_type(x, 1.0))
+    if model is not None:
+        out[:, 7:13] = model.forward(pack_input(x, u))
+    return out
+
+
+def flatten_params(Ws: List[np.ndarray], bs: List[np.ndarray]) -> np.ndarray:
+    """Parameters as one vector, layer by layer: W_l row-major then b_l."""
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in zip(Ws, bs)])

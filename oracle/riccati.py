@@ -1,0 +1,121 @@
+"""Feedback-phase LQ solve in float64 -- TEST INFRASTRUCTURE.
+
+The QP of Sec. IV-A with a Gauss-Newton Hessian of the quadratic tracking cost
+(Sec. VI, MPC cost formulation) and the continuity condition eq. (2), without
+the inequality rows eq. (3):
+
+    min  sum_{k<N} 1/2 [dx;du]^T blkdiag(Q,R) [dx;du] + q_k^T dx + r_k^T du
+         + 1/2 dx_N^T Q_N dx_N + q_N^T dx_N
+    s.t. dx_{k+1} = A_k dx_k + B_k du_k + c_k,   c_k = phi-bar_k - x_{k+1}
+
+The optimal step is du_k = K_k dx_k + kff_k.  ``riccati`` is the backward
+dynamic-programming recursion; ``kkt_bruteforce`` solves the same QP as one
+dense equality-constrained linear system and is used only to check it.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+
+def riccati(A, B, Q, R, QN, c=None, q=None, r=None, qN=None):
+    """One instance.  A (N,13,13), B (N,13,4) -> K (N,4,13), kff (N,4), P (N+1,13,13).
+
+    The value function after step k is 1/2 dx^T P_k dx + p_k^T dx."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    N, nx, nu = B.shape
+    c = np.zeros((N, nx)) if c is None else np.asarray(c, dtype=np.float64)
+    q = np.zeros((N, nx)) if q is None else np.asarray(q, dtype=np.float64)
+    r = np.zeros((N, nu)) if r is None else np.asarray(r, dtype=np.float64)
+    qN = np.zeros(nx) if qN is None else np.asarray(qN, dtype=np.float64)
+    K = np.zeros((N, nu, nx))
+    kff = np.zeros((N, nu))
+    Ps = np.zeros((N + 1, nx, nx))
+    P = np.array(QN, dtype=np.float64)
+    p = qN.copy()
+    Ps[N] = P
+    for k in range(N - 1, -1, -1):
+        Ak, Bk = A[k], B[k]
+        Qxx = Q + Ak.T @ P @ Ak
+        Quu = R + Bk.T @ P @ Bk
+        Qux = Bk.T @ P @ Ak
+        gvec = P @ c[k] + p
+        qx = q[k] + Ak.T @ gvec
+        qu = r[k] + Bk.T @ gvec
+        K[k] = -np.linalg.solve(Quu, Qux)
+        kff[k] = -np.linalg.solve(Quu, qu)
+        P = Qxx + Qux.T @ K[k]
+        P = 0.5 * (P + P.T)
+        p = qx + Qux.T @ kff[k]
+        Ps[k] = P
+    return K, kff, Ps
+
+
+def riccati_batched(offsets, A, B, Q, R, QN, c=None, q=None, r=None, qN=None):
+    """Apply ``riccati`` to each CSR instance range.  Returns K, kff, P (node-major)."""
+    offsets = np.asarray(offsets)
+    n = int(offsets[-1])
+    nx, nu = B.shape[1], B.shape[2]
+    K = np.zeros((n, nu, nx))
+    kff = np.zeros((n, nu))
+    P = np.zeros((n, nx, nx))
+    for i in range(len(offsets) - 1):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        Ki, ki, Pi = riccati(A[a:b], B[a:b], Q, R, QN,
+                             None if c is None else c[a:b],
+                             None if q is None else q[a:b],
+                             None if r is None else r[a:b],
+                             None if qN is None else qN[i])
+        K[a:b], kff[a:b], P[a:b] = Ki, ki, Pi[:-1]
+    return K, kff, P
+
+
+def kkt_bruteforce(A, B, Q, R, QN, dx0, c=None, q=None, r=None, qN=None):
+    """Solve the whole QP for a given initial deviation dx0 as one KKT system.
+
+    Decision vector z = [dx_0, du_0, dx_1, du_1, ..., dx_N].  Returns (du (N,4), dx (N+1,13))."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    N, nx, nu = B.shape
+    c = np.zeros((N, nx)) if c is None else c
+    q = np.zeros((N, nx)) if q is None else q
+    r = np.zeros((N, nu)) if r is None else r
+    qN = np.zeros(nx) if qN is None else qN
+    nz = N * (nx + nu) + nx
+    H = np.zeros((nz, nz))
+    h = np.zeros(nz)
+
+    def xi(k):
+        return k * (nx + nu)
+
+    def ui(k):
+        return k * (nx + nu) + nx
+
+    for k in range(N):
+        H[xi(k):xi(k) + nx, xi(k):xi(k) + nx] = Q
+        H[ui(k):ui(k) + nu, ui(k):ui(k) + nu] = R
+        h[xi(k):xi(k) + nx] = q[k]
+        h[ui(k):ui(k) + nu] = r[k]
+    H[xi(N):xi(N) + nx, xi(N):xi(N) + nx] = QN
+    h[xi(N):xi(N) + nx] = qN
+    # equality rows: dx_0 = dx0;  dx_{k+1} - A dx_k - B du_k = c_k
+    neq = (N + 1) * nx
+    E = np.zeros((neq, nz))
+    e = np.zeros(neq)
+    E[0:nx, 0:nx] = np.eye(nx)
+    e[0:nx] = dx0
+    for k in range(N):
+        rows = slice((k + 1) * nx, (k + 2) * nx)
+        E[rows, xi(k + 1):xi(k + 1) + nx] = np.eye(nx)
+        E[rows, xi(k):xi(k) + nx] = -A[k]
+        E[rows, ui(k):ui(k) + nu] = -B[k]
+        e[rows] = c[k]
+    KKT = np.block([[H, E.T], [E, np.zeros((neq, neq))]])
+    rhs = np.concatenate([-h, e])
+    sol = np.linalg.solve(KKT, rhs)
+    z = sol[:nz]
+    du = np.stack([z[ui(k):ui(k) + nu] for k in range(N)])
+    dx = np.stack([z[xi(k):xi(k) + nx] for k in range(N + 1)])
+    return du, dx

@@ -1,0 +1,216 @@
+/*
+ * rtn.h -- C ABI of the MI355X (gfx950) linearisation path of Real-time Neural MPC
+ * (Salzmann et al., "Real-time Neural MPC: Deep Learning Model Predictive Control
+ * for Quadrotors and Agile Robotic Platforms", RA-L 2023).
+ *
+ * What the library computes
+ * -------------------------
+ * Sec. IV-A: every SQP iteration needs, at every shooting node k of every MPC
+ * instance, the continuity-condition parameters of the QP (eq. (2) and the
+ * definitions below it):
+ *     phi-bar_k = phi(x_k, u_k, f, dt),  A_k = d phi/d x_k,  B_k = d phi/d u_k,
+ * where phi is one explicit RK4 step (Sec. III) of f = f_F + f_D: the nominal
+ * quadrotor model f_F (eq. (6)) plus a learned residual network f_D (eq. (7)).
+ * Real-time Neural MPC evaluates the network and its Jacobian once per node, as
+ * one batch (Sec. IV-A), and forms phi, A_k and B_k with the network replaced by
+ * its first-order local approximation f_D-bar + J_D [x - x_k; u - u_k] (eq. (4),
+ * first order per Sec. IV-B).  rtn_linearize does exactly that on the GPU.
+ * rtn_riccati solves the unconstrained LQ subproblem built from A_k, B_k (the
+ * feedback phase, Sec. IV-B); rtn_train_step fits the residual network
+ * (Sec. VII).
+ *
+ * Conventions for every function
+ * ------------------------------
+ *  - Return value is an rtn_status; RTN_OK (0) on success, a negative code
+ *    otherwise, with a message available from rtn_last_error() (thread-local).
+ *    Nothing aborts and no C++ exception crosses this interface.
+ *  - All arguments are validated on the host before any work is enqueued.  On an
+ *    error nothing has been enqueued and no output is guaranteed.
+ *  - "device" pointers point to memory of the current HIP device; "host"
+ *    pointers to ordinary CPU memory.  The caller owns every array argument and
+ *    must keep device arrays alive until the stream has finished the call.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are stream-ordered and return before the GPU work completes, except where a
+ *    function is documented as synchronous.
+ *  - All arrays are row-major and node-major: node i of instance j is global
+ *    node offsets[j] + i.  State x = [p(3), q(4) = (w,x,y,z), v(3), omega(3)]
+ *    (13 floats), input u = rotor thrusts T_0..T_3 (4 floats), eq. (6).
+ *  - A model may not be used from two streams at the same time (it owns
+ *    workspace that calls share).
+ */
+#ifndef RTN_H
+#define RTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rtn_status;
+#define RTN_OK 0
+#define RTN_EINVAL (-1)   /* invalid argument (message names it) */
+#define RTN_ENOMEM (-2)   /* device or host allocation failed */
+#define RTN_EHIP (-3)     /* a HIP runtime call failed (message holds its error string) */
+#define RTN_ENOTSUP (-4)  /* valid request the library does not support (e.g. width) */
+
+/* Arithmetic of the network part of a call.  RTN_FP32: fp32 matrix cores.
+ * RTN_BF16: bfloat16 weights and activations, fp32 accumulation.
+ * RTN_FP8: OCP FP8 E4M3 weights, activations and cotangents with static
+ * per-tensor scales (see rtn_model_calibrate), fp32 accumulation.  In every mode
+ * bias, activation, its derivative, f_D-bar, J_D and the RK4 chain are fp32. */
+typedef enum { RTN_FP32 = 0, RTN_BF16 = 1, RTN_FP8 = 2 } rtn_precision;
+
+/* Hidden-layer activation: SiLU a*logistic(a), or identity (linear network). */
+typedef enum { RTN_ACT_SILU = 0, RTN_ACT_IDENTITY = 1 } rtn_activation;
+
+/* Residual network descriptor (naming N-L-W of Sec. VII: L hidden layers of
+ * width W).  d_in must be 14 (input [v, omega, q, u]) and d_out 6 (linear and
+ * angular acceleration residuals, eq. (7)).  width must be one of 64, 128, 256,
+ * 512, 1024; 1 <= n_hidden <= 16. */
+typedef struct {
+    int32_t d_in;
+    int32_t d_out;
+    int32_t n_hidden;
+    int32_t width;
+    int32_t activation; /* rtn_activation */
+} rtn_mlp_desc;
+
+/* Quadrotor constants of eq. (6): mass [kg], diagonal inertia [kg m^2], arm =
+ * centre-to-rotor distance of the X frame [m], c_tau = rotor reaction torque per
+ * newton of thrust [m], g = gravity magnitude [m/s^2] (acting along -z world).
+ * Rotor i sits at body (x,y) = arm/sqrt(2) * {(+,-), (-,-), (-,+), (+,+)}[i];
+ * rotors 0 and 2 spin counter-clockwise, 1 and 3 clockwise (Fig. quad_model). */
+typedef struct {
+    float mass, Jx, Jy, Jz, arm, c_tau, g;
+} rtn_quad;
+
+typedef struct rtn_model rtn_model;
+
+/* Library version string, static storage. */
+const char* rtn_version(void);
+
+/* Message of the last failing call on this thread ("" if none), valid until the
+ * next failing call on the same thread. */
+const char* rtn_last_error(void);
+
+/* Number of float parameters of a network: for l = 1..L+1 the weight matrix
+ * W_l [fan_out][fan_in] row-major (the convention y = W x + b) followed by the
+ * bias b_l [fan_out].  This is the layout of every params_host buffer below. */
+rtn_status rtn_param_count(const rtn_mlp_desc* desc, int64_t* count);
+
+/* Create a model on the current device and copy the parameters (host, float,
+ * rtn_param_count floats) into library-owned device memory.  The library
+ * owns everything reachable from the model: fp32 master parameters, packed
+ * bf16/fp8 copies, fp8 scales, gradients, Adam moments and workspace.
+ * Synchronous.  *out is NULL on error. */
+rtn_status rtn_model_create(const rtn_mlp_desc* desc, const float* params_host, rtn_model** out);
+
+/* Free a model and everything it owns (synchronises the device first).  NULL is a no-op. */
+rtn_status rtn_model_destroy(rtn_model* model);
+
+/* Replace / read back the fp32 master parameters (host buffers, layout as
+ * rtn_param_count).  Synchronous.  Setting parameters resets nothing else. */
+rtn_status rtn_model_set_params(rtn_model* model, const float* params_host);
+rtn_status rtn_model_get_params(rtn_model* model, float* params_host);
+
+/* Static FP8 scales.  Weight scales are amax(|W_l|)/448 and are refreshed
+ * whenever parameters change.  Activation and cotangent scales are measured by
+ * running the network and its reverse sweep in fp32 over n calibration nodes
+ * (device x [n][13], u [n][4]) and taking amax/448 per tensor.  Synchronous.
+ * RTN_FP8 calls on an uncalibrated model fail with RTN_EINVAL. */
+rtn_status rtn_model_calibrate(rtn_model* model, int32_t n, const float* x, const float* u, void* stream);
+
+/* Copy the scales to host: scales[0 .. 3L+2) = { weight scale of W_1..W_{L+1},
+ * activation scale of z_0, h_1..h_L (L+1 values... index L+1..2L+1),
+ * cotangent scale of layers L..1 (index 2L+2..3L+1) }.  *n_scales = 3L+2.
+ * Values are 0 before calibration. */
+rtn_status rtn_model_get_scales(const rtn_model* model, float* scales_host, int32_t* n_scales);
+
+/* The hot path: continuity parameters of every node, eq. (2) with eq. (4).
+ *   model      network f_D, or NULL for the nominal model alone (f_D = 0)
+ *   prec       arithmetic of the network part (ignored when model is NULL)
+ *   quad       host, quadrotor constants
+ *   dt         RK4 step [s], > 0
+ *   n_inst     number of MPC instances >= 1; offsets_host (host, int32
+ *              [n_inst+1]) their node ranges: offsets[0] = 0, non-decreasing,
+ *              offsets[n_inst] = n_nodes, each instance >= 1 node.  NULL means a
+ *              single instance (n_inst must then be 1).  Nodes are independent,
+ *              so offsets only describe the batch; they do not change results.
+ *   n_nodes    total nodes >= 0 (0 is a valid empty call)
+ *   x, u       device, fp32 [n][13], [n][4]: the iterate (x_k, u_k)
+ * outputs (device, fp32):
+ *   x_next     [n][13]      phi-bar_k
+ *   A          [n][13][13]  A[k][i][j] = d x_{k+1,i} / d x_{k,j}
+ *   B          [n][13][4]   B[k][i][j] = d x_{k+1,i} / d u_{k,j}
+ *   f_D        nullable [n][6]      network output at the node (f_D-bar)
+ *   J_D        nullable [n][6][14]  its Jacobian w.r.t. [v, omega, q, u]
+ *   status     nullable uint8 [n]: 0 ok; bit0 non-finite network output or
+ *              Jacobian; bit1 non-finite x_next, A or B.
+ * The linearisation point (x_k, u_k, f_D-bar, J_D) is held fixed inside the RK4
+ * step; A_k, B_k are the exact derivatives of that discrete map. */
+rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const rtn_quad* quad, float dt,
+                         int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                         const float* x, const float* u,
+                         float* x_next, float* A, float* B,
+                         float* f_D, float* J_D, uint8_t* status, void* stream);
+
+/* Feedback phase: backward Riccati recursion of the LQ problem
+ *   min sum_k 1/2 [dx;du]^T blkdiag(Q,R) [dx;du] + q_k^T dx + r_k^T du
+ *       + 1/2 dx_N^T Q_N dx_N + qN^T dx_N
+ *   s.t. dx_{k+1} = A_k dx_k + B_k du_k + c_k          (eq. (2))
+ * per instance, in fp64.  The optimal step is du_k = K_k dx_k + kff_k.
+ *   offsets_host  as in rtn_linearize (NULL: one instance)
+ *   A, B          device fp32 [n][13][13], [n][13][4] (promoted exactly)
+ *   c             device fp64 nullable [n][13]: defects phi-bar_k - x_{k+1}
+ *   Q_host, R_host, QN_host  host fp64 13x13, 4x4, 13x13 (symmetric; R + B^T P B
+ *                 must be positive definite)
+ *   q, r          device fp64 nullable [n][13], [n][4]; qN nullable [n_inst][13]
+ * outputs (device fp64): K [n][4][13], kff [n][4], P nullable [n][13][13] = the
+ * value-function Hessian P_k at node k (before the step at k is taken). */
+rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                       const float* A, const float* B, const double* c,
+                       const double* Q_host, const double* R_host, const double* QN_host,
+                       const double* q, const double* r, const double* qN,
+                       double* K, double* kff, double* P, void* stream);
+
+/* Network forward pass over a batch (device in [batch][14] -> out [batch][6]),
+ * stashing what rtn_mlp_backward needs in the model.  prec RTN_FP32 or RTN_BF16. */
+rtn_status rtn_mlp_forward(rtn_model* model, int32_t prec, int32_t batch,
+                           const float* in, float* out, void* stream);
+
+/* Backward pass of the last rtn_mlp_forward (same batch): given dL/dout
+ * (device [batch][6]), ADD dL/dparams into the model's gradient buffer and, if
+ * din is not NULL, write dL/din (device [batch][14]). */
+rtn_status rtn_mlp_backward(rtn_model* model, int32_t batch, const float* dout, float* din,
+                            void* stream);
+
+/* Zero the gradient buffer; copy it to host (rtn_param_count floats, synchronous). */
+rtn_status rtn_model_zero_grad(rtn_model* model, void* stream);
+rtn_status rtn_model_get_grad(rtn_model* model, float* grad_host);
+
+/* One Adam step (bias-corrected, no weight decay) on the fp32 master parameters
+ * from the gradient buffer; increments the model's step counter and refreshes
+ * the packed copies. */
+rtn_status rtn_adam_step(rtn_model* model, float lr, float beta1, float beta2, float eps,
+                         void* stream);
+
+/* Fused training step (Sec. VII): forward, loss = mean over (batch, 6) of
+ * (net(in) - target)^2, backward, Adam.  in [batch][14], target [batch][6]
+ * device fp32; loss (device fp32 scalar, nullable) receives the loss before the
+ * update.  prec RTN_FP32 or RTN_BF16 (the matrix products; master weights and
+ * Adam state are fp32). */
+rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch,
+                          const float* in, const float* target,
+                          float lr, float beta1, float beta2, float eps,
+                          float* loss, void* stream);
+
+/* Adam state to host: m and v (rtn_param_count floats each, nullable) and the step. */
+rtn_status rtn_model_get_adam(rtn_model* model, float* m_host, float* v_host, int64_t* step);
+rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float* v_host, int64_t step);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTN_H */

@@ -66,12 +66,18 @@ def affine_field(x_k, u_k, y_bar, J, quad: QuadParams = QUAD):
 
 
 def linearize_affine(x: np.ndarray, u: np.ndarray, model: Optional[MLP], dt: float,
-                     quad: QuadParams = QUAD):
-    """(x_next (n,13), A (n,13,13), B (n,13,4), f_D-bar (n,6), J_D (n,6,14))."""
+                     quad: QuadParams = QUAD, params=None):
+    """(x_next (n,13), A (n,13,13), B (n,13,4), f_D-bar (n,6), J_D (n,6,14)).
+
+    ``params`` = (f_D-bar, J_D) supplies the local approximation's parameters
+    directly (e.g. from a reduced-precision evaluation of the network)."""
     x = np.asarray(x, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
     n = x.shape[0]
-    y_bar, J = node_parameters(model, x, u)
+    if params is None:
+        y_bar, J = node_parameters(model, x, u)
+    else:
+        y_bar, J = (np.asarray(a, dtype=np.float64) for a in params)
     f_bar, J_x, J_u = residual_in_state(y_bar, J)
 
     # S = d x_s / d [x_k, u_k] (n, 13, 17); stage derivative K_s and dK_s.

@@ -1,0 +1,201 @@
+"""Real-time Neural MPC linearisation path on MI355X (gfx950).
+
+Thin Python binding of librtn.so (C ABI in include/rtn.h).  Arrays are torch
+tensors on the GPU; this module only checks and marshals arguments -- every
+step of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: if librtn.so is missing or the tensors are not on a GPU, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import PREC, ACT, MlpDesc, Quad, check, load
+
+__all__ = ["Model", "linearize", "riccati", "version", "quad_struct", "PREC"]
+
+
+def version() -> str:
+    return load().rtn_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, shape, name):
+    """Check a device tensor's dtype/shape/contiguity and return its address."""
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def quad_struct(q) -> Quad:
+    return Quad(q.mass, q.Jx, q.Jy, q.Jz, q.arm, q.c_tau, q.g)
+
+
+class Model:
+    """A residual network owned by the library (fp32 master weights on the GPU)."""
+
+    def __init__(self, Ws: Sequence[np.ndarray], bs: Sequence[np.ndarray], activation: str = "silu"):
+        L = len(Ws) - 1
+        width = Ws[0].shape[0]
+        self.desc = MlpDesc(Ws[0].shape[1], Ws[-1].shape[0], L, width, ACT[activation])
+        self.n_hidden, self.width = L, width
+        flat = self._flatten(Ws, bs)
+        n = ctypes.c_int64()
+        check(load().rtn_param_count(ctypes.byref(self.desc), ctypes.byref(n)), "rtn_param_count")
+        if n.value != flat.size:
+            raise ValueError(f"parameter count {flat.size} does not match the descriptor ({n.value})")
+        h = ctypes.c_void_p()
+        check(load().rtn_model_create(ctypes.byref(self.desc), flat.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(h)), "rtn_model_create")
+        self._h = h
+        self.n_params = n.value
+
+    @staticmethod
+    def _flatten(Ws, bs) -> np.ndarray:
+        parts = []
+        for W, b in zip(Ws, bs):
+            parts += [np.ascontiguousarray(W, dtype=np.float32).ravel(), np.ascontiguousarray(b, dtype=np.float32).ravel()]
+        return np.ascontiguousarray(np.concatenate(parts), dtype=np.float32)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("model has been closed")
+        return self._h
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(load().rtn_model_get_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)), "rtn_model_get_params")
+        return out
+
+    def set_params(self, Ws, bs) -> None:
+        flat = self._flatten(Ws, bs)
+        check(load().rtn_model_set_params(self.handle, flat.ctypes.data_as(ctypes.c_void_p)), "rtn_model_set_params")
+
+    def calibrate(self, x, u, stream=None) -> None:
+        torch = _torch()
+        n = x.shape[0]
+        check(load().rtn_model_calibrate(self.handle, n, _dev(x, torch.float32, (n, 13), "x"),
+                                         _dev(u, torch.float32, (n, 4), "u"), _stream(stream)),
+              "rtn_model_calibrate")
+
+    def scales(self) -> np.ndarray:
+        k = ctypes.c_int32()
+        check(load().rtn_model_get_scales(self.handle, None, ctypes.byref(k)), "rtn_model_get_scales")
+        out = np.zeros(k.value, dtype=np.float32)
+        check(load().rtn_model_get_scales(self.handle, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(k)),
+              "rtn_model_get_scales")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            load().rtn_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def linearize(x, u, model: Optional[Model] = None, prec: str = "fp32", dt: float = 0.05, quad=None,
+              offsets: Optional[np.ndarray] = None, want_fd: bool = True, want_status: bool = False,
+              out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
+    """rtn_linearize over device tensors x [n,13], u [n,4] (fp32).
+
+    Returns a dict with x_next [n,13], A [n,13,13], B [n,13,4] and, on request,
+    f_D [n,6], J_D [n,6,14], status [n] (uint8).  ``out`` may supply the output
+    tensors to avoid allocation."""
+    torch = _torch()
+    from workload import QUAD
+    q = quad_struct(quad if quad is not None else QUAD)
+    n = x.shape[0]
+    dev = x.device
+    if out is None:
+        out = {}
+    def get(name, shape, dtype=torch.float32):
+        t = out.get(name)
+        if t is None:
+            t = torch.empty(shape, dtype=dtype, device=dev)
+            out[name] = t
+        return t
+    xn = get("x_next", (n, 13))
+    A = get("A", (n, 13, 13))
+    B = get("B", (n, 13, 4))
+    fD = get("f_D", (n, 6)) if want_fd else None
+    JD = get("J_D", (n, 6, 14)) if want_fd else None
+    st = get("status", (n,), torch.uint8) if want_status else None
+    if offsets is None:
+        n_inst, off_ptr, off_arr = 1, None, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    check(load().rtn_linearize(model.handle if model is not None else None, PREC[prec], ctypes.byref(q),
+                               ctypes.c_float(dt), n_inst, off_ptr, n,
+                               _dev(x, torch.float32, (n, 13), "x"), _dev(u, torch.float32, (n, 4), "u"),
+                               _dev(xn, torch.float32, (n, 13), "x_next"), _dev(A, torch.float32, (n, 13, 13), "A"),
+                               _dev(B, torch.float32, (n, 13, 4), "B"),
+                               _dev(fD, torch.float32, (n, 6), "f_D") if fD is not None else None,
+                               _dev(JD, torch.float32, (n, 6, 14), "J_D") if JD is not None else None,
+                               _dev(st, torch.uint8, (n,), "status") if st is not None else None,
+                               _stream(stream)), "rtn_linearize")
+    return out
+
+
+def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_P: bool = False,
+            out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
+    """rtn_riccati over device tensors A [n,13,13], B [n,13,4] (fp32); Q, R, QN host arrays (fp64).
+
+    Returns K [n,4,13], kff [n,4] and optionally P [n,13,13] (fp64 device tensors)."""
+    torch = _torch()
+    n = A.shape[0]
+    dev = A.device
+    if out is None:
+        out = {}
+    K = out.setdefault("K", torch.empty((n, 4, 13), dtype=torch.float64, device=dev))
+    kff = out.setdefault("kff", torch.empty((n, 4), dtype=torch.float64, device=dev))
+    P = out.setdefault("P", torch.empty((n, 13, 13), dtype=torch.float64, device=dev)) if want_P else None
+    if offsets is None:
+        n_inst, off_ptr = 1, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    Qh = np.ascontiguousarray(Q, dtype=np.float64)
+    Rh = np.ascontiguousarray(R, dtype=np.float64)
+    QNh = np.ascontiguousarray(QN, dtype=np.float64)
+    f64 = torch.float64
+    check(load().rtn_riccati(n_inst, off_ptr, n, _dev(A, torch.float32, (n, 13, 13), "A"),
+                             _dev(B, torch.float32, (n, 13, 4), "B"),
+                             _dev(c, f64, (n, 13), "c") if c is not None else None,
+                             Qh.ctypes.data_as(ctypes.c_void_p), Rh.ctypes.data_as(ctypes.c_void_p),
+                             QNh.ctypes.data_as(ctypes.c_void_p),
+                             _dev(q, f64, (n, 13), "q") if q is not None else None,
+                             _dev(r, f64, (n, 4), "r") if r is not None else None,
+                             _dev(qN, f64, (n_inst, 13), "qN") if qN is not None else None,
+                             _dev(K, f64, (n, 4, 13), "K"), _dev(kff, f64, (n, 4), "kff"),
+                             _dev(P, f64, (n, 13, 13), "P") if P is not None else None,
+                             _stream(stream)), "rtn_riccati")
+    return out

@@ -1,0 +1,46 @@
+// Host-visible interface of the network kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace rtn {
+
+// Device view of a network, passed by value to the kernels.  Layer index i is
+// 0-based: fw[i] packs W_{i+1} (M = fan_out, K = fan_in), rw[i] packs W_{i+1}^T
+// (M = fan_in, K = fan_out) for the hidden layers i < L.
+struct NetView {
+  int L;    // hidden layers
+  int act;  // 0 SiLU, 1 identity
+  const void* fw[17];
+  const void* rw[16];
+  const float* bias[17];
+  const float* w_out;   // fp32 W_{L+1} [6][H]
+  const float* wscale;  // fp8: dequantisation scale of W_1..W_{L+1} (L+1)
+  const float* ascale;  // fp8: scale of the forward operands z_0, h_1..h_L (L+1)
+  const float* gscale;  // fp8: scale of the reverse operands G_1..G_L (L)
+};
+
+template <int P> struct StashT { using type = uint16_t; };
+template <> struct StashT<0> { using type = float; };
+
+int pack_geometry(int prec, int M, int K, int* MT, int* KS);
+hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int trans, const float* scale, void* out,
+                       hipStream_t st);
+hipError_t launch_amax(const float* a, long n, float* out, hipStream_t st);
+hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st);
+hipError_t launch_mlp_forward(int prec, int H, const NetView& net, int n, const float* x, const float* u,
+                              const float* zin, void* stash, float* y, float* amax, hipStream_t st);
+hipError_t launch_mlp_reverse(int prec, int H, const NetView& net, int n, const void* stash, float* J, float* amax,
+                              hipStream_t st);
+int stash_elem_bytes(int prec);
+
+struct QuadConst {
+  float mass, Jx, Jy, Jz, arm, c_tau, g;
+};
+hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
+                                const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st);
+
+}  // namespace rtn

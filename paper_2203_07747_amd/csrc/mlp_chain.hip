@@ -1,0 +1,503 @@
+// Residual network value and Jacobian on matrix cores (gfx950).
+//
+// Sec. IV-A evaluates the learned dynamics and its Jacobian for all shooting
+// nodes as one batch.  Here the batch is a matrix of rows (one row per node for
+// the forward pass, six rows per node -- one per network output -- for the
+// reverse/adjoint sweep) and every layer is a product with the same weight
+// matrix, so the whole batch is a chain of GEMMs.
+//
+// Layer-chain kernels.  One workgroup owns a block of R rows and carries it
+// through every layer: the block's activations (forward) or cotangents
+// (reverse) live in LDS as the B operand, each wave streams its slice of the
+// weight matrix (the A operand) from L2, and the fp32 accumulators of a layer
+// are written straight back to LDS as the next layer's operand.  We compute the
+// transposed product C^T = W . H^T so that an accumulator register already is
+// an operand slot (see slot_feature in common.h) and the write-back needs no
+// transpose.  Weights are stored pre-packed in exact fragment order, so every
+// weight load is one contiguous 64-lane vector load.
+//
+//   forward  : a_l = W_l h_{l-1} + b_l, h_l = act(a_l); stash act'(a_l); y = W_{L+1} h_L + b_{L+1}
+//   reverse  : G_L = W_{L+1} * act'(a_L) (per node, 6 rows); G_{l-1} = (G_l W_l) * act'(a_{l-1});
+//              J_D = G_1 W_1            (chain rule: J_D = W_{L+1} D_L W_L ... D_1 W_1)
+//
+// The activation-derivative stash goes through HBM between the two kernels
+// (L * H values per node).
+#include "common.h"
+#include "mlp_chain.h"
+
+namespace rtn {
+
+// Rows per workgroup and waves per workgroup for a (precision, width) pair.
+// Limits: the B operand of R rows x H features must fit in LDS, and each wave's
+// accumulators (H/32/NW M-tiles x R/32 row tiles x 16 floats) must stay <= 128
+// registers.
+template <int P, int H> struct ChainShape {
+  static constexpr int NW = H >= 256 ? 8 : H / 32;
+  static constexpr int R = P == P_FP32 ? (H <= 256 ? 128 : (H == 512 ? 64 : 32))
+                         : P == P_BF16 ? (H <= 256 ? 128 : (H == 512 ? 96 : 64))
+                                       : (H <= 512 ? 128 : 64);
+};
+
+template <int P, int H, int R, int NW> struct Chain {
+  using M = Mfma<P>;
+  using elem = typename M::elem;
+  using frag = typename M::frag;
+  static constexpr int E = M::E, KSTEP = M::KSTEP;
+  static constexpr int RT = R / 32;
+  static constexpr int MT = H / 32;
+  static constexpr int MTW = MT / NW;
+  static constexpr int KS_H = H / KSTEP;
+  static constexpr int K1 = (kDin + M::KALIGN - 1) / M::KALIGN * M::KALIGN;
+  static constexpr int KS_1 = K1 / KSTEP;
+  static constexpr int B_BYTES = R * H * (int)sizeof(elem);
+  static constexpr int PART_BYTES = NW * R * 16 * 4;
+  static constexpr int LDS_BYTES = B_BYTES > PART_BYTES ? B_BYTES : PART_BYTES;
+  static_assert(MT % NW == 0, "width must split evenly over the waves");
+  static_assert(MTW * RT * 16 <= 128, "accumulator budget");
+
+  // LDS element index of (row tile, K-step, lane, slot-in-step) for an operand with KS K-steps.
+  __device__ static inline int lidx(int rt, int s, int lane, int KS) { return ((rt * KS + s) * kWave + lane) * E; }
+
+  __device__ static inline frag lds_frag(const elem* lds, int rt, int s, int lane, int KS) {
+    return *reinterpret_cast<const frag*>(lds + lidx(rt, s, lane, KS));
+  }
+
+  // acc[i][r] = sum_s A(mt0+i, s) * B(r, s) over K-steps [s0, s1), NMT M-tiles.
+  template <int NMT>
+  __device__ static inline void gemm(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int KS, int mt0,
+                                     int s0, int s1, const elem* lds, int lane) {
+#pragma unroll
+    for (int i = 0; i < NMT; ++i)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[i][r] = f32x16{};
+    if (s0 >= s1) return;
+    frag a[NMT];
+#pragma unroll
+    for (int i = 0; i < NMT; ++i) a[i] = Wp[((mt0 + i) * KS + s0) * kWave + lane];
+    for (int s = s0; s < s1; ++s) {
+      frag an[NMT];
+      const int sn = s + 1 < s1 ? s + 1 : s;
+#pragma unroll
+      for (int i = 0; i < NMT; ++i) an[i] = Wp[((mt0 + i) * KS + sn) * kWave + lane];
+      frag b[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) b[r] = lds_frag(lds, r, s, lane, KS);
+#pragma unroll
+      for (int i = 0; i < NMT; ++i)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[i][r] = M::mma(a[i], b[r], acc[i][r]);
+#pragma unroll
+      for (int i = 0; i < NMT; ++i) a[i] = an[i];
+    }
+  }
+
+  // K-step range of wave w when a narrow (one M-tile) layer splits its K over the waves.
+  __device__ static inline void split_k(int w, int* s0, int* s1) {
+    constexpr int per = (KS_H + NW - 1) / NW;
+    *s0 = w * per < KS_H ? w * per : KS_H;
+    *s1 = *s0 + per < KS_H ? *s0 + per : KS_H;
+  }
+
+  // Store 16 accumulator-ordered values of (row tile rt, M-tile mt) as operand slots
+  // q = 16*mt .. 16*mt+15 of the next layer (K-steps over width H).
+  __device__ static inline void put_operand(elem* lds, int rt, int mt, int lane, const float (&v)[16], float inv_scale) {
+    if constexpr (P == P_FP32) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[lidx(rt, 16 * mt + i, lane, KS_H)] = v[i];
+    } else if constexpr (P == P_BF16) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        i32x4 w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          w[j] = (int)((uint32_t)f32_to_bf16_rne(v[8 * h + 2 * j]) | ((uint32_t)f32_to_bf16_rne(v[8 * h + 2 * j + 1]) << 16));
+        *reinterpret_cast<i32x4*>(lds + lidx(rt, 2 * mt + h, lane, KS_H)) = w;
+      }
+    } else {
+      i32x4 w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        w[j] = (int)(f32x2_to_e4m3(v[4 * j] * inv_scale, v[4 * j + 1] * inv_scale) |
+                     (f32x2_to_e4m3(v[4 * j + 2] * inv_scale, v[4 * j + 3] * inv_scale) << 16));
+      *reinterpret_cast<i32x4*>(lds + lidx(rt, mt >> 1, lane, KS_H) + (mt & 1) * 16) = w;
+    }
+  }
+
+  // Write one operand element block (E slots of lane `lane`, K-step s) from float values.
+  __device__ static inline void put_slots(elem* lds, int rt, int s, int lane, int KS, const float* v, float inv_scale) {
+    elem* dst = lds + lidx(rt, s, lane, KS);
+    if constexpr (P == P_FP32) {
+      dst[0] = v[0];
+    } else if constexpr (P == P_BF16) {
+      i32x4 w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = (int)((uint32_t)f32_to_bf16_rne(v[2 * j]) | ((uint32_t)f32_to_bf16_rne(v[2 * j + 1]) << 16));
+      *reinterpret_cast<i32x4*>(dst) = w;
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        i32x4 w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          w[j] = (int)(f32x2_to_e4m3(v[16 * h + 4 * j] * inv_scale, v[16 * h + 4 * j + 1] * inv_scale) |
+                       (f32x2_to_e4m3(v[16 * h + 4 * j + 2] * inv_scale, v[16 * h + 4 * j + 3] * inv_scale) << 16));
+        *reinterpret_cast<i32x4*>(dst + 16 * h) = w;
+      }
+    }
+  }
+};
+
+__device__ inline void atomic_amax(float* p, float v) {
+  // non-negative floats order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
+}
+
+template <typename S> __device__ inline S to_stash(float v);
+template <> __device__ inline float to_stash<float>(float v) { return v; }
+template <> __device__ inline uint16_t to_stash<uint16_t>(float v) { return f32_to_bf16_rne(v); }
+__device__ inline float from_stash(float v) { return v; }
+__device__ inline float from_stash(uint16_t v) { return bf16_to_f32(v); }
+
+// ---------------------------------------------------------------------------
+// Forward chain: z_0 -> h_1..h_L (stash act'), y.
+template <int P, int H>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H>::NW * kWave)))
+mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* __restrict__ u,
+                  const float* __restrict__ zin, typename StashT<P>::type* __restrict__ stash,
+                  float* __restrict__ y, float* __restrict__ amax) {
+  constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
+  using C = Chain<P, H, R, NW>;
+  using elem = typename C::elem;
+  using frag = typename C::frag;
+  using S = typename StashT<P>::type;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[C::LDS_BYTES];
+  elem* lds = reinterpret_cast<elem*>(smem);
+  float* part = reinterpret_cast<float*>(smem);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
+  const int nblocks = (n + R - 1) / R;
+  const float* dq = net.wscale;  // fp8 only
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int row0 = blk * R;
+    // z_0 = [v, omega, q, u] into operand slots of K1 features
+    for (int it = tid; it < C::RT * C::KS_1 * kWave; it += NW * kWave) {
+      const int l = it % kWave, s = (it / kWave) % C::KS_1, rt = it / (kWave * C::KS_1);
+      const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
+      float v[C::E];
+#pragma unroll
+      for (int j = 0; j < C::E; ++j) {
+        const int k = slot_feature(s * C::E + j, gg);
+        float z = 0.f;
+        if (row < n && k < kDin) {
+          if (zin) z = zin[(size_t)row * kDin + k];
+          else if (k < 6) z = x[(size_t)row * kNx + 7 + k];          // v, omega
+          else if (k < 10) z = x[(size_t)row * kNx + 3 + (k - 6)];   // q
+          else z = u[(size_t)row * kNu + (k - 10)];                  // u
+        }
+        v[j] = z;
+        if (amax && row < n && k < kDin) atomic_amax(&amax[0], z);
+      }
+      C::put_slots(lds, rt, s, l, C::KS_1, v, P == P_FP8 ? 1.f / net.ascale[0] : 1.f);
+    }
+    __syncthreads();
+
+    for (int layer = 0; layer < net.L; ++layer) {
+      const int KS = layer == 0 ? C::KS_1 : C::KS_H;
+      f32x16 acc[C::MTW][C::RT];
+      C::template gemm<C::MTW>(acc, reinterpret_cast<const frag*>(net.fw[layer]), KS, wave * C::MTW, 0, KS, lds, lane);
+      __syncthreads();
+      const float scale = P == P_FP8 ? dq[layer] * net.ascale[layer] : 1.f;
+      const float inv_next = P == P_FP8 ? 1.f / net.ascale[layer + 1] : 1.f;
+      const float* bias = net.bias[layer];
+      S* st = stash + (size_t)layer * n * H;
+#pragma unroll
+      for (int i = 0; i < C::MTW; ++i) {
+        const int mt = wave * C::MTW + i;
+#pragma unroll
+        for (int r = 0; r < C::RT; ++r) {
+          const int row = row0 + r * 32 + (lane & 31);
+          float h[16], sp[16];
+#pragma unroll
+          for (int vi = 0; vi < 16; ++vi) {
+            const int m = mt * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3);
+            const float a = acc[i][r][vi] * scale + bias[m];
+            if (net.act == 0) {
+              const float sg = 1.f / (1.f + __expf(-a));
+              h[vi] = a * sg;
+              sp[vi] = sg * (1.f + a * (1.f - sg));
+            } else {
+              h[vi] = a;
+              sp[vi] = 1.f;
+            }
+            if (amax && row < n) atomic_amax(&amax[layer + 1], h[vi]);
+          }
+          if (row < n) {
+            S* dst = st + (size_t)row * H + mt * 32 + g * 16;
+#pragma unroll
+            for (int vi = 0; vi < 16; ++vi) dst[vi] = to_stash<S>(sp[vi]);
+          }
+          C::put_operand(lds, r, mt, lane, h, inv_next);
+        }
+      }
+      __syncthreads();
+    }
+
+    // output layer y = W_{L+1} h_L + b: one 32-row M-tile (6 used), K split over the waves
+    {
+      f32x16 acc[1][C::RT];
+      int s0, s1;
+      C::split_k(wave, &s0, &s1);
+      C::template gemm<1>(acc, reinterpret_cast<const frag*>(net.fw[net.L]), C::KS_H, 0, s0, s1, lds, lane);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < C::RT; ++r)
+#pragma unroll
+        for (int vi = 0; vi < 4; ++vi) part[(wave * R + r * 32 + (lane & 31)) * 8 + g * 4 + vi] = acc[0][r][vi];
+      __syncthreads();
+      const float scale = P == P_FP8 ? dq[net.L] * net.ascale[net.L] : 1.f;
+      for (int t = tid; t < R * kDout; t += NW * kWave) {
+        const int rr = t / kDout, j = t % kDout, row = row0 + rr;
+        float s = 0.f;
+        for (int w = 0; w < NW; ++w) s += part[(w * R + rr) * 8 + j];
+        if (row < n) y[(size_t)row * kDout + j] = s * scale + net.bias[net.L][j];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse (adjoint) chain: 6 rows per node; J_D[node][j][c] for the 14 inputs.
+template <int P, int H>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H>::NW * kWave)))
+mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict__ stash,
+                  float* __restrict__ J, float* __restrict__ amax) {
+  constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
+  using C = Chain<P, H, R, NW>;
+  using elem = typename C::elem;
+  using frag = typename C::frag;
+  using S = typename StashT<P>::type;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[C::LDS_BYTES];
+  elem* lds = reinterpret_cast<elem*>(smem);
+  float* part = reinterpret_cast<float*>(smem);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
+  const int nrows = 6 * n;
+  const int nblocks = (nrows + R - 1) / R;
+  const int L = net.L;
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int row0 = blk * R;
+    // G_L[row][k] = W_{L+1}[row % 6][k] * act'(a_L)[row / 6][k]
+    {
+      const S* spL = stash + (size_t)(L - 1) * n * H;
+      const float inv = P == P_FP8 ? 1.f / net.gscale[L - 1] : 1.f;
+      for (int it = tid; it < C::RT * C::KS_H * kWave; it += NW * kWave) {
+        const int l = it % kWave, s = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
+        const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
+        float v[C::E];
+        const int node = row / 6, j6 = row - 6 * (row / 6);
+#pragma unroll
+        for (int j = 0; j < C::E; ++j) {
+          const int k = slot_feature(s * C::E + j, gg);
+          v[j] = row < nrows ? net.w_out[j6 * H + k] * from_stash(spL[(size_t)node * H + stash_pos(k)]) : 0.f;
+          if (amax && row < nrows) atomic_amax(&amax[L - 1], v[j]);
+        }
+        C::put_slots(lds, rt, s, l, C::KS_H, v, inv);
+      }
+    }
+    __syncthreads();
+
+    for (int layer = L - 1; layer >= 1; --layer) {  // weights W_{layer+1}^T, stash of h_layer
+      f32x16 acc[C::MTW][C::RT];
+      C::template gemm<C::MTW>(acc, reinterpret_cast<const frag*>(net.rw[layer]), C::KS_H, wave * C::MTW, 0, C::KS_H, lds, lane);
+      __syncthreads();
+      const float scale = P == P_FP8 ? net.wscale[layer] * net.gscale[layer] : 1.f;
+      const float inv_next = P == P_FP8 ? 1.f / net.gscale[layer - 1] : 1.f;
+      const S* sp = stash + (size_t)(layer - 1) * n * H;
+#pragma unroll
+      for (int i = 0; i < C::MTW; ++i) {
+        const int mt = wave * C::MTW + i;
+#pragma unroll
+        for (int r = 0; r < C::RT; ++r) {
+          const int row = row0 + r * 32 + (lane & 31);
+          const int node = row < nrows ? row / 6 : 0;
+          const S* src = sp + (size_t)node * H + mt * 32 + g * 16;
+          float v[16];
+#pragma unroll
+          for (int vi = 0; vi < 16; ++vi) {
+            v[vi] = acc[i][r][vi] * scale * from_stash(src[vi]);
+            if (amax && row < nrows) atomic_amax(&amax[layer - 1], v[vi]);
+          }
+          C::put_operand(lds, r, mt, lane, v, inv_next);
+        }
+      }
+      __syncthreads();
+    }
+
+    // J_D = G_1 W_1: one M-tile (14 used), K split over the waves
+    {
+      f32x16 acc[1][C::RT];
+      int s0, s1;
+      C::split_k(wave, &s0, &s1);
+      C::template gemm<1>(acc, reinterpret_cast<const frag*>(net.rw[0]), C::KS_H, 0, s0, s1, lds, lane);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < C::RT; ++r)
+#pragma unroll
+        for (int vi = 0; vi < 8; ++vi)
+          part[(wave * R + r * 32 + (lane & 31)) * 16 + (vi >> 2) * 8 + g * 4 + (vi & 3)] = acc[0][r][vi];
+      __syncthreads();
+      const float scale = P == P_FP8 ? net.wscale[0] * net.gscale[0] : 1.f;
+      for (int t = tid; t < R * kDin; t += NW * kWave) {
+        const int rr = t / kDin, c = t % kDin, row = row0 + rr;
+        float s = 0.f;
+        for (int w = 0; w < NW; ++w) s += part[(w * R + rr) * 16 + c];
+        if (row < nrows) J[(size_t)row * kDin + c] = s * scale;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operand packing: fp32 matrix -> fragment-ordered compute-type copy.
+//   out[((mt*KS + s)*64 + lane)*E + j] = A[m][k],  m = 32 mt + lane % 32,
+//   k = slot_feature(s*E + j, lane / 32);  A = W (trans = 0) or W^T (trans = 1),
+//   W fp32 row-major [rows][cols].  Zero outside M x K.
+template <int P>
+__global__ void pack_operand(const float* __restrict__ W, int cols, int M, int K, int trans,
+                             const float* __restrict__ scale, typename Mfma<P>::elem* __restrict__ out,
+                             int MT, int KS) {
+  constexpr int E = Mfma<P>::E;
+  const long total = (long)MT * KS * kWave * E;
+  const float inv = (P == P_FP8 && scale) ? 1.f / scale[0] : 1.f;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int j = idx % E;
+    const int lane = (idx / E) % kWave;
+    const int s = (idx / ((long)E * kWave)) % KS;
+    const int mt = idx / ((long)E * kWave * KS);
+    const int m = mt * 32 + (lane & 31);
+    const int k = slot_feature(s * E + j, lane >> 5);
+    float v = 0.f;
+    if (m < M && k < K) v = trans ? W[(size_t)k * cols + m] : W[(size_t)m * cols + k];
+    if constexpr (P == P_FP32) out[idx] = v;
+    else if constexpr (P == P_BF16) out[idx] = f32_to_bf16_rne(v);
+    else out[idx] = (uint8_t)(f32x2_to_e4m3(v * inv, 0.f) & 0xffu);
+  }
+}
+
+__global__ void amax_kernel(const float* __restrict__ a, long n, float* __restrict__ out) {
+  float m = 0.f;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) m = fmaxf(m, fabsf(a[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomic_amax(out, m);
+}
+
+// amax -> e4m3 scale (amax / 448, 1 when the tensor is all zero)
+__global__ void amax_to_scale(float* s, int n) {
+  int i = threadIdx.x;
+  if (i < n) s[i] = s[i] > 0.f ? s[i] / 448.f : 1.f;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+
+int pack_geometry(int prec, int M, int K, int* MT, int* KS) {
+  int E, KSTEP, KALIGN;
+  if (prec == P_FP32) { E = 1; KSTEP = 2; KALIGN = 16; }
+  else if (prec == P_BF16) { E = 8; KSTEP = 16; KALIGN = 16; }
+  else { E = 32; KSTEP = 64; KALIGN = 64; }
+  (void)E;
+  *MT = (M + 31) / 32;
+  *KS = round_up(K, KALIGN) / KSTEP;
+  return *MT * *KS * kWave * E;  // elements
+}
+
+hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int trans, const float* scale, void* out,
+                       hipStream_t st) {
+  int MT, KS;
+  long total = pack_geometry(prec, M, K, &MT, &KS);
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (prec == P_FP32)
+    pack_operand<P_FP32><<<blocks, 256, 0, st>>>(W, cols, M, K, trans, scale, (float*)out, MT, KS);
+  else if (prec == P_BF16)
+    pack_operand<P_BF16><<<blocks, 256, 0, st>>>(W, cols, M, K, trans, scale, (uint16_t*)out, MT, KS);
+  else
+    pack_operand<P_FP8><<<blocks, 256, 0, st>>>(W, cols, M, K, trans, scale, (uint8_t*)out, MT, KS);
+  return hipGetLastError();
+}
+
+hipError_t launch_amax(const float* a, long n, float* out, hipStream_t st) {
+  amax_kernel<<<64, 256, 0, st>>>(a, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st) {
+  amax_to_scale<<<1, 64, 0, st>>>(s, n);
+  return hipGetLastError();
+}
+
+static int g_num_cu = 0;
+static int num_cu() {
+  if (!g_num_cu) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) g_num_cu = p.multiProcessorCount;
+    if (g_num_cu <= 0) g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+template <int P, int H>
+static hipError_t fwd_impl(const NetView& net, int n, const float* x, const float* u, const float* zin, void* stash,
+                           float* y, float* amax, hipStream_t st, int grid_cap) {
+  constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
+  int blocks = (n + R - 1) / R;
+  int grid = blocks < grid_cap ? blocks : grid_cap;
+  if (grid <= 0) return hipSuccess;
+  mlp_forward_chain<P, H><<<grid, NW * kWave, 0, st>>>(net, n, x, u, zin, (typename StashT<P>::type*)stash, y, amax);
+  return hipGetLastError();
+}
+
+template <int P, int H>
+static hipError_t rev_impl(const NetView& net, int n, const void* stash, float* J, float* amax, hipStream_t st,
+                           int grid_cap) {
+  constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
+  int blocks = (6 * n + R - 1) / R;
+  int grid = blocks < grid_cap ? blocks : grid_cap;
+  if (grid <= 0) return hipSuccess;
+  mlp_reverse_chain<P, H><<<grid, NW * kWave, 0, st>>>(net, n, (const typename StashT<P>::type*)stash, J, amax);
+  return hipGetLastError();
+}
+
+#define RTN_DISPATCH_H(P, FN, ...)                 \
+  switch (H) {                                      \
+    case 64: return FN<P, 64>(__VA_ARGS__);         \
+    case 128: return FN<P, 128>(__VA_ARGS__);       \
+    case 256: return FN<P, 256>(__VA_ARGS__);       \
+    case 512: return FN<P, 512>(__VA_ARGS__);       \
+    case 1024: return FN<P, 1024>(__VA_ARGS__);     \
+    default: return hipErrorInvalidValue;           \
+  }
+
+hipError_t launch_mlp_forward(int prec, int H, const NetView& net, int n, const float* x, const float* u,
+                              const float* zin, void* stash, float* y, float* amax, hipStream_t st) {
+  const int cap = 2 * num_cu();
+  if (prec == P_FP32) { RTN_DISPATCH_H(P_FP32, fwd_impl, net, n, x, u, zin, stash, y, amax, st, cap) }
+  if (prec == P_BF16) { RTN_DISPATCH_H(P_BF16, fwd_impl, net, n, x, u, zin, stash, y, amax, st, cap) }
+  RTN_DISPATCH_H(P_FP8, fwd_impl, net, n, x, u, zin, stash, y, amax, st, cap)
+}
+
+hipError_t launch_mlp_reverse(int prec, int H, const NetView& net, int n, const void* stash, float* J, float* amax,
+                              hipStream_t st) {
+  const int cap = 2 * num_cu();
+  if (prec == P_FP32) { RTN_DISPATCH_H(P_FP32, rev_impl, net, n, stash, J, amax, st, cap) }
+  if (prec == P_BF16) { RTN_DISPATCH_H(P_BF16, rev_impl, net, n, stash, J, amax, st, cap) }
+  RTN_DISPATCH_H(P_FP8, rev_impl, net, n, stash, J, amax, st, cap)
+}
+
+int stash_elem_bytes(int prec) { return prec == P_FP32 ? 4 : 2; }
+
+}  // namespace rtn

@@ -1,0 +1,53 @@
+// The model object behind rtn_model*: everything it owns lives in device memory
+// allocated by the library and is freed by rtn_model_destroy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/rtn.h"
+#include "mlp_chain.h"
+
+namespace rtn {
+
+struct Model {
+  rtn_mlp_desc desc{};
+  int L = 0, H = 0;
+  int64_t n_params = 0;
+  int64_t w_off[kMaxHidden + 1] = {}, b_off[kMaxHidden + 1] = {};
+  float* params = nullptr;  // fp32 master copy, layout of rtn_param_count
+  float* grad = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  int64_t adam_step = 0;
+  // per-precision operand copies in MFMA fragment order
+  void* packed_fw[3][kMaxHidden + 1] = {};
+  void* packed_rw[3][kMaxHidden] = {};
+  // fp8 scales: weights [0, L], forward operands [L+1, 2L+1], reverse operands [2L+2, 3L+1]
+  float* scales = nullptr;
+  bool calibrated = false;
+  // workspace (grown on demand)
+  void* stash = nullptr;
+  size_t stash_bytes = 0;
+  float* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  std::vector<void*> allocs;
+
+  ~Model();
+  rtn_status init(const rtn_mlp_desc& d);
+  rtn_status alloc(void** p, size_t bytes);
+  void release(void* p);
+  rtn_status repack(hipStream_t st);
+  rtn_status ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st);
+  NetView view(int prec) const;
+  int64_t layer_fan_in(int l) const;
+  int64_t layer_fan_out(int l) const;
+  static int elem_bytes(int prec);
+};
+
+rtn_status hip_fail(hipError_t e, const char* what);
+rtn_status inval(const char* fmt, const char* arg);
+rtn_status check_offsets(int32_t n_inst, const int32_t* offsets, int32_t n_nodes);
+
+}  // namespace rtn

@@ -1,0 +1,232 @@
+// One RK4 step of the nominal quadrotor model plus the node's affine residual,
+// with its exact sensitivities -- the continuity parameters of the QP
+// (Sec. IV-A, eq. (2) and the definitions that follow it; local approximation
+// eq. (4); quadrotor model eq. (6); RK4 as in Sec. III).
+//
+//   F(x) = f_F(x, u_k) + f_D-bar + J_x (x - x_k)        (u held constant)
+//   k_s  = F(x_k + c_s dt k_{s-1}),  c = (0, 1/2, 1/2, 1)
+//   x_{k+1} = x_k + dt/6 (k_1 + 2 k_2 + 2 k_3 + k_4)
+//   [A | B] = d x_{k+1} / d [x_k, u_k], carried as 13-vector tangents through the
+//   four stages:  dk_s = (df_F/dx + J_x) dx_s  (+ df_F/du_j + J_u e_j for input j).
+//
+// Work split: 16 lanes per node (4 nodes per wave).  Lane c < 10 carries the
+// tangent of state column 3 + c (nothing depends on the position, so columns
+// 0..2 of A are the identity's and need no work); lanes 10..13 carry input
+// columns 0..3; lane 14 writes x_{k+1}; lane 15 writes A's position columns.
+// Every lane recomputes the node's state trajectory (cheap) so no lane waits
+// on another.
+#include "common.h"
+#include "mlp_chain.h"
+
+namespace rtn {
+
+constexpr int kNodesPerBlock = 16;
+constexpr int kNodeStride = 108;  // x 13 | u 4 | y 6 | J 84 | pad 1
+
+
+// f_F(x, u) with T = sum u, tau from the X-frame mixer; closed form of eq. (6).
+__device__ inline void nominal_rhs(const float* x, const float* u, const QuadConst& P, float* f) {
+  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const float wx = x[10], wy = x[11], wz = x[12];
+  const float T = u[0] + u[1] + u[2] + u[3];
+  const float h = P.arm * 0.70710678118654752f;
+  f[0] = x[7];
+  f[1] = x[8];
+  f[2] = x[9];
+  f[3] = 0.5f * (-qx * wx - qy * wy - qz * wz);
+  f[4] = 0.5f * (qw * wx + qy * wz - qz * wy);
+  f[5] = 0.5f * (qw * wy - qx * wz + qz * wx);
+  f[6] = 0.5f * (qw * wz + qx * wy - qy * wx);
+  const float Tm = T / P.mass;
+  f[7] = Tm * 2.f * (qx * qz + qw * qy);
+  f[8] = Tm * 2.f * (qy * qz - qw * qx);
+  f[9] = Tm * (qw * qw - qx * qx - qy * qy + qz * qz) - P.g;
+  const float tx = h * (-u[0] - u[1] + u[2] + u[3]);
+  const float ty = h * (-u[0] + u[1] + u[2] - u[3]);
+  const float tz = P.c_tau * (-u[0] + u[1] - u[2] + u[3]);
+  f[10] = (tx - (P.Jz - P.Jy) * wy * wz) / P.Jx;
+  f[11] = (ty - (P.Jx - P.Jz) * wz * wx) / P.Jy;
+  f[12] = (tz - (P.Jy - P.Jx) * wx * wy) / P.Jz;
+}
+
+// (df_F/dx) d at x (directional derivative along the state tangent d).
+__device__ inline void nominal_tangent(const float* x, const float* u, const QuadConst& P, const float* d,
+                                       float* df) {
+  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const float wx = x[10], wy = x[11], wz = x[12];
+  const float dqw = d[3], dqx = d[4], dqy = d[5], dqz = d[6];
+  const float dwx = d[10], dwy = d[11], dwz = d[12];
+  const float T = u[0] + u[1] + u[2] + u[3];
+  df[0] = d[7];
+  df[1] = d[8];
+  df[2] = d[9];
+  // product rule on q (x) (0, w) / 2
+  df[3] = 0.5f * (-dqx * wx - dqy * wy - dqz * wz - qx * dwx - qy * dwy - qz * dwz);
+  df[4] = 0.5f * (dqw * wx + dqy * wz - dqz * wy + qw * dwx + qy * dwz - qz * dwy);
+  df[5] = 0.5f * (dqw * wy - dqx * wz + dqz * wx + qw * dwy - qx * dwz + qz * dwx);
+  df[6] = 0.5f * (dqw * wz + dqx * wy - dqy * wx + qw * dwz + qx * dwy - qy * dwx);
+  const float Tm = T / P.mass;
+  df[7] = Tm * 2.f * (dqx * qz + qx * dqz + dqw * qy + qw * dqy);
+  df[8] = Tm * 2.f * (dqy * qz + qy * dqz - dqw * qx - qw * dqx);
+  df[9] = Tm * 2.f * (qw * dqw - qx * dqx - qy * dqy + qz * dqz);
+  df[10] = -(P.Jz - P.Jy) * (dwy * wz + wy * dwz) / P.Jx;
+  df[11] = -(P.Jx - P.Jz) * (dwz * wx + wz * dwx) / P.Jy;
+  df[12] = -(P.Jy - P.Jx) * (dwx * wy + wx * dwy) / P.Jz;
+}
+
+// J_x d restricted to rows 7..12 (network inputs are v, omega, q).
+__device__ inline void residual_tangent(const float* J, const float* d, float* out6) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const float* Jr = J + r * kDin;
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s += Jr[c] * d[7 + c] + Jr[3 + c] * d[10 + c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s += Jr[6 + c] * d[3 + c];
+    out6[r] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, const float* __restrict__ u,
+                     const float* __restrict__ fD, const float* __restrict__ JD, float* __restrict__ xn,
+                     float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status) {
+  __shared__ float sm[kNodesPerBlock * kNodeStride];
+  __shared__ int flags[kNodesPerBlock];
+  const int tid = threadIdx.x;
+  const int node0 = blockIdx.x * kNodesPerBlock;
+  const int nn = min(kNodesPerBlock, n - node0);
+  if (nn <= 0) return;
+  // cooperative, coalesced staging of the block's node data
+  for (int i = tid; i < nn * kNx; i += 256) sm[(i / kNx) * kNodeStride + (i % kNx)] = x[(size_t)node0 * kNx + i];
+  for (int i = tid; i < nn * kNu; i += 256) sm[(i / kNu) * kNodeStride + 13 + (i % kNu)] = u[(size_t)node0 * kNu + i];
+  for (int i = tid; i < nn * kDout; i += 256)
+    sm[(i / kDout) * kNodeStride + 17 + (i % kDout)] = fD ? fD[(size_t)node0 * kDout + i] : 0.f;
+  for (int i = tid; i < nn * kDout * kDin; i += 256)
+    sm[(i / (kDout * kDin)) * kNodeStride + 23 + (i % (kDout * kDin))] = JD ? JD[(size_t)node0 * kDout * kDin + i] : 0.f;
+  if (tid < kNodesPerBlock) flags[tid] = 0;
+  __syncthreads();
+
+  const int ln = tid >> 4, c = tid & 15;
+  const bool active = ln < nn;
+  const int node = node0 + ln;
+  const float* s = sm + (active ? ln : 0) * kNodeStride;
+  const float* xk = s;
+  const float* uk = s + 13;
+  const float* yb = s + 17;
+  const float* J = s + 23;
+
+  // which tangent this lane carries
+  const int xcol = c < 10 ? 3 + c : -1;
+  const int ucol = (c >= 10 && c < 14) ? c - 10 : -1;
+  const float h = P.arm * 0.70710678118654752f;
+  float fu[13];  // df_F/du_j + J_u e_j (state-independent parts added per stage)
+  if (ucol >= 0) {
+    const float sx[4] = {-1.f, -1.f, 1.f, 1.f}, sy[4] = {-1.f, 1.f, 1.f, -1.f}, sz[4] = {-1.f, 1.f, -1.f, 1.f};
+#pragma unroll
+    for (int i = 0; i < 13; ++i) fu[i] = 0.f;
+    fu[10] = h * sx[ucol] / P.Jx;
+    fu[11] = h * sy[ucol] / P.Jy;
+    fu[12] = P.c_tau * sz[ucol] / P.Jz;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) fu[7 + r] += J[r * kDin + 10 + ucol];
+  }
+
+  float xs[13], kp[13], ks[13], dk[13], dkp[13], ds[13], accx[13], accd[13];
+#pragma unroll
+  for (int i = 0; i < 13; ++i) { accx[i] = 0.f; accd[i] = 0.f; kp[i] = 0.f; dkp[i] = 0.f; }
+  const float cst[4] = {0.f, 0.5f, 0.5f, 1.f};
+  const float wst[4] = {1.f, 2.f, 2.f, 1.f};
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const float cdt = cst[st] * dt;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+      xs[i] = xk[i] + cdt * kp[i];
+      ds[i] = ((i == xcol) ? 1.f : 0.f) + cdt * dkp[i];
+    }
+    // stage derivative of the state
+    nominal_rhs(xs, uk, P, ks);
+    float dx[13], r6[6];
+#pragma unroll
+    for (int i = 0; i < 13; ++i) dx[i] = xs[i] - xk[i];
+    residual_tangent(J, dx, r6);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) ks[7 + r] += yb[r] + r6[r];
+    // stage derivative of the tangent
+    nominal_tangent(xs, uk, P, ds, dk);
+    residual_tangent(J, ds, r6);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) dk[7 + r] += r6[r];
+    if (ucol >= 0) {
+      // thrust direction at the stage point (the homogeneous q (.) e_z)
+      const float qw = xs[3], qx = xs[4], qy = xs[5], qz = xs[6];
+      dk[7] += 2.f * (qx * qz + qw * qy) / P.mass;
+      dk[8] += 2.f * (qy * qz - qw * qx) / P.mass;
+      dk[9] += (qw * qw - qx * qx - qy * qy + qz * qz) / P.mass;
+#pragma unroll
+      for (int i = 7; i < 13; ++i) dk[i] += fu[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+      accx[i] += wst[st] * ks[i];
+      accd[i] += wst[st] * dk[i];
+      kp[i] = ks[i];
+      dkp[i] = dk[i];
+    }
+  }
+
+  const float dt6 = dt / 6.f;
+  int bad = 0;
+  if (active && c < 14) {
+    float col[13];
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+      col[i] = ((i == xcol) ? 1.f : 0.f) + dt6 * accd[i];
+      bad |= !isfinite(col[i]);
+    }
+    if (xcol >= 0) {
+      float* Ab = A + (size_t)node * kNx * kNx + xcol;
+#pragma unroll
+      for (int i = 0; i < 13; ++i) Ab[i * kNx] = col[i];
+    } else {
+      float* Bb = B + (size_t)node * kNx * kNu + ucol;
+#pragma unroll
+      for (int i = 0; i < 13; ++i) Bb[i * kNu] = col[i];
+    }
+  } else if (active && c == 14) {
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+      const float v = xk[i] + dt6 * accx[i];
+      bad |= !isfinite(v);
+      xn[(size_t)node * kNx + i] = v;
+    }
+  } else if (active) {
+    float* Ab = A + (size_t)node * kNx * kNx;
+#pragma unroll
+    for (int i = 0; i < 13; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ab[i * kNx + j] = (i == j) ? 1.f : 0.f;
+  }
+  if (status) {  // uniform over the block
+    int mlp_bad = 0;
+    if (active && c == 15) {
+      for (int i = 0; i < 6; ++i) mlp_bad |= !isfinite(yb[i]);
+      for (int i = 0; i < 84; ++i) mlp_bad |= !isfinite(J[i]);
+    }
+    if (active && (bad || mlp_bad)) atomicOr(&flags[ln], (bad ? 2 : 0) | (mlp_bad ? 1 : 0));
+    __syncthreads();
+    if (active && c == 0) status[node] = (uint8_t)flags[ln];
+  }
+}
+
+hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
+                                const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + kNodesPerBlock - 1) / kNodesPerBlock;
+  rk4_linearize_kernel<<<blocks, 256, 0, st>>>(n, q, dt, x, u, fD, JD, xn, A, B, status);
+  return hipGetLastError();
+}
+
+}  // namespace rtn

@@ -1,0 +1,363 @@
+// C ABI of the library: argument validation, model ownership and dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtn.h"
+#include "mlp_chain.h"
+#include "model.h"
+
+using namespace rtn;
+
+namespace {
+
+thread_local std::string g_err;
+
+rtn_status fail(rtn_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace
+
+rtn_status rtn::hip_fail(hipError_t e, const char* what) {
+  return fail(RTN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+rtn_status rtn::inval(const char* fmt, const char* arg) { return fail(RTN_EINVAL, fmt, arg); }
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// model object
+
+static bool width_supported(int w) { return w == 64 || w == 128 || w == 256 || w == 512 || w == 1024; }
+
+static rtn_status check_desc(const rtn_mlp_desc* d) {
+  if (!d) return fail(RTN_EINVAL, "desc is NULL");
+  if (d->d_in != kDin) return fail(RTN_EINVAL, "d_in must be 14 (got %d)", d->d_in);
+  if (d->d_out != kDout) return fail(RTN_EINVAL, "d_out must be 6 (got %d)", d->d_out);
+  if (d->n_hidden < 1 || d->n_hidden > kMaxHidden)
+    return fail(RTN_EINVAL, "n_hidden must be in [1, 16] (got %d)", d->n_hidden);
+  if (d->activation != RTN_ACT_SILU && d->activation != RTN_ACT_IDENTITY)
+    return fail(RTN_EINVAL, "unknown activation %d", d->activation);
+  if (d->width <= 0) return fail(RTN_EINVAL, "width must be positive (got %d)", d->width);
+  if (!width_supported(d->width)) return fail(RTN_ENOTSUP, "width %d not supported (64, 128, 256, 512, 1024)", d->width);
+  return RTN_OK;
+}
+
+int64_t rtn::Model::layer_fan_in(int l) const { return l == 0 ? desc.d_in : desc.width; }
+int64_t rtn::Model::layer_fan_out(int l) const { return l == desc.n_hidden ? desc.d_out : desc.width; }
+
+static int64_t count_params(const rtn_mlp_desc& d) {
+  int64_t n = 0;
+  for (int l = 0; l <= d.n_hidden; ++l) {
+    int64_t fi = l == 0 ? d.d_in : d.width, fo = l == d.n_hidden ? d.d_out : d.width;
+    n += fo * fi + fo;
+  }
+  return n;
+}
+
+rtn::Model::~Model() {
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+rtn_status rtn::Model::alloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+  if (e != hipSuccess) return fail(RTN_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  allocs.push_back(*p);
+  return RTN_OK;
+}
+
+void rtn::Model::release(void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < allocs.size(); ++i)
+    if (allocs[i] == p) {
+      allocs.erase(allocs.begin() + i);
+      break;
+    }
+  (void)hipFree(p);
+}
+
+rtn_status rtn::Model::init(const rtn_mlp_desc& d) {
+  desc = d;
+  L = d.n_hidden;
+  H = d.width;
+  n_params = count_params(d);
+  int64_t off = 0;
+  for (int l = 0; l <= L; ++l) {
+    w_off[l] = off;
+    off += layer_fan_out(l) * layer_fan_in(l);
+    b_off[l] = off;
+    off += layer_fan_out(l);
+  }
+  rtn_status s;
+  if ((s = alloc((void**)&params, n_params * 4))) return s;
+  if ((s = alloc((void**)&grad, n_params * 4))) return s;
+  if ((s = alloc((void**)&adam_m, n_params * 4))) return s;
+  if ((s = alloc((void**)&adam_v, n_params * 4))) return s;
+  if ((s = alloc((void**)&scales, (3 * L + 2) * 4))) return s;
+  HIP_TRY(hipMemset(grad, 0, n_params * 4));
+  HIP_TRY(hipMemset(adam_m, 0, n_params * 4));
+  HIP_TRY(hipMemset(adam_v, 0, n_params * 4));
+  HIP_TRY(hipMemset(scales, 0, (3 * L + 2) * 4));
+  for (int p = 0; p < 3; ++p) {
+    for (int l = 0; l <= L; ++l) {
+      int MT, KS;
+      size_t elems = pack_geometry(p, (int)layer_fan_out(l), (int)layer_fan_in(l), &MT, &KS);
+      if ((s = alloc(&packed_fw[p][l], elems * elem_bytes(p)))) return s;
+      if (l < L) {
+        elems = pack_geometry(p, (int)layer_fan_in(l), (int)layer_fan_out(l), &MT, &KS);
+        if ((s = alloc(&packed_rw[p][l], elems * elem_bytes(p)))) return s;
+      }
+    }
+  }
+  return RTN_OK;
+}
+
+int rtn::Model::elem_bytes(int prec) { return prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1; }
+
+NetView rtn::Model::view(int prec) const {
+  NetView v;
+  memset(&v, 0, sizeof v);
+  v.L = L;
+  v.act = desc.activation == RTN_ACT_SILU ? 0 : 1;
+  for (int l = 0; l <= L; ++l) {
+    v.fw[l] = packed_fw[prec][l];
+    v.bias[l] = params + b_off[l];
+    if (l < L) v.rw[l] = packed_rw[prec][l];
+  }
+  v.w_out = params + w_off[L];
+  v.wscale = scales;
+  v.ascale = scales + (L + 1);
+  v.gscale = scales + 2 * (L + 1);
+  return v;
+}
+
+// Refresh packed copies of the fp32 master weights (and the fp8 weight scales).
+rtn_status rtn::Model::repack(hipStream_t st) {
+  for (int l = 0; l <= L; ++l) {
+    int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
+    HIP_TRY(hipMemsetAsync(scales + l, 0, 4, st));
+    HIP_TRY(launch_amax(params + w_off[l], (long)fo * fi, scales + l, st));
+  }
+  HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
+  for (int p = 0; p < 3; ++p) {
+    for (int l = 0; l <= L; ++l) {
+      int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
+      HIP_TRY(launch_pack(p, params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[p][l], st));
+      if (l < L) HIP_TRY(launch_pack(p, params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[p][l], st));
+    }
+  }
+  return RTN_OK;
+}
+
+rtn_status rtn::Model::ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st) {
+  (void)nrow_train;
+  const size_t need = (size_t)L * n * H * 4;  // fp32 stash is the largest
+  if (need > stash_bytes) {
+    if (stash) {
+      HIP_TRY(hipStreamSynchronize(st));
+      release(stash);
+      stash = nullptr;
+    }
+    stash_bytes = 0;
+    rtn_status s = alloc(&stash, need);
+    if (s) return s;
+    stash_bytes = need;
+  }
+  const size_t need_y = (size_t)n * (kDout + kDout * kDin) * 4;
+  if (need_y > tmp_bytes) {
+    if (tmp) {
+      HIP_TRY(hipStreamSynchronize(st));
+      release(tmp);
+      tmp = nullptr;
+    }
+    tmp_bytes = 0;
+    rtn_status s = alloc((void**)&tmp, need_y);
+    if (s) return s;
+    tmp_bytes = need_y;
+  }
+  return RTN_OK;
+}
+
+extern "C" {
+
+const char* rtn_version(void) { return "rtn-mi355x 0.1 (gfx950)"; }
+
+const char* rtn_last_error(void) { return g_err.c_str(); }
+
+rtn_status rtn_param_count(const rtn_mlp_desc* desc, int64_t* count) {
+  rtn_status s = check_desc(desc);
+  if (s) return s;
+  if (!count) return fail(RTN_EINVAL, "count is NULL");
+  *count = count_params(*desc);
+  return RTN_OK;
+}
+
+rtn_status rtn_model_create(const rtn_mlp_desc* desc, const float* params_host, rtn_model** out) {
+  if (!out) return fail(RTN_EINVAL, "out is NULL");
+  *out = nullptr;
+  rtn_status s = check_desc(desc);
+  if (s) return s;
+  if (!params_host) return fail(RTN_EINVAL, "params_host is NULL");
+  Model* m = new (std::nothrow) Model();
+  if (!m) return fail(RTN_ENOMEM, "host allocation of the model failed");
+  if ((s = m->init(*desc))) {
+    delete m;
+    return s;
+  }
+  hipError_t e = hipMemcpy(m->params, params_host, m->n_params * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "hipMemcpy(params)");
+  }
+  if ((s = m->repack(nullptr))) {
+    delete m;
+    return s;
+  }
+  e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "hipStreamSynchronize");
+  }
+  *out = reinterpret_cast<rtn_model*>(m);
+  return RTN_OK;
+}
+
+rtn_status rtn_model_destroy(rtn_model* model) {
+  if (!model) return RTN_OK;
+  (void)hipDeviceSynchronize();
+  delete reinterpret_cast<Model*>(model);
+  return RTN_OK;
+}
+
+rtn_status rtn_model_set_params(rtn_model* model, const float* params_host) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  if (!params_host) return fail(RTN_EINVAL, "params_host is NULL");
+  Model* m = reinterpret_cast<Model*>(model);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(m->params, params_host, m->n_params * 4, hipMemcpyHostToDevice));
+  rtn_status s = m->repack(nullptr);
+  if (s) return s;
+  HIP_TRY(hipStreamSynchronize(nullptr));
+  return RTN_OK;
+}
+
+rtn_status rtn_model_get_params(rtn_model* model, float* params_host) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  if (!params_host) return fail(RTN_EINVAL, "params_host is NULL");
+  Model* m = reinterpret_cast<Model*>(model);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(params_host, m->params, m->n_params * 4, hipMemcpyDeviceToHost));
+  return RTN_OK;
+}
+
+rtn_status rtn_model_calibrate(rtn_model* model, int32_t n, const float* x, const float* u, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  if (n <= 0) return fail(RTN_EINVAL, "calibration needs n >= 1 nodes (got %d)", n);
+  if (!x || !u) return fail(RTN_EINVAL, "x and u must be device pointers");
+  Model* m = reinterpret_cast<Model*>(model);
+  hipStream_t st = (hipStream_t)stream;
+  rtn_status s = m->ensure_workspace(n, 0, st);
+  if (s) return s;
+  const int L = m->L;
+  float* a_amax = m->scales + (L + 1);
+  float* g_amax = m->scales + 2 * (L + 1);
+  HIP_TRY(hipMemsetAsync(a_amax, 0, (2 * L + 1) * 4, st));
+  NetView v = m->view(P_FP32);
+  float* y = m->tmp;
+  float* J = m->tmp + (size_t)n * kDout;
+  HIP_TRY(launch_mlp_forward(P_FP32, m->H, v, n, x, u, nullptr, m->stash, y, a_amax, st));
+  HIP_TRY(launch_mlp_reverse(P_FP32, m->H, v, n, m->stash, J, g_amax, st));
+  HIP_TRY(launch_amax_to_scale(a_amax, 2 * L + 1, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  m->calibrated = true;
+  return RTN_OK;
+}
+
+rtn_status rtn_model_get_scales(const rtn_model* model, float* scales_host, int32_t* n_scales) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  const Model* m = reinterpret_cast<const Model*>(model);
+  if (n_scales) *n_scales = 3 * m->L + 2;
+  if (scales_host) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(scales_host, m->scales, (3 * m->L + 2) * 4, hipMemcpyDeviceToHost));
+    if (!m->calibrated)
+      for (int i = m->L + 1; i < 3 * m->L + 2; ++i) scales_host[i] = 0.f;
+  }
+  return RTN_OK;
+}
+
+}  // extern "C"
+
+// validation shared by the batched entry points
+rtn_status rtn::check_offsets(int32_t n_inst, const int32_t* offsets, int32_t n_nodes) {
+  if (n_nodes < 0) return fail(RTN_EINVAL, "n_nodes must be >= 0 (got %d)", n_nodes);
+  if (n_inst < 1) return fail(RTN_EINVAL, "n_inst must be >= 1 (got %d)", n_inst);
+  if (!offsets) {
+    if (n_inst != 1) return fail(RTN_EINVAL, "offsets_host is NULL but n_inst = %d (must be 1)", n_inst);
+    return RTN_OK;
+  }
+  if (offsets[0] != 0) return fail(RTN_EINVAL, "offsets[0] must be 0 (got %d)", offsets[0]);
+  for (int i = 0; i < n_inst; ++i)
+    if (offsets[i + 1] <= offsets[i])
+      return fail(RTN_EINVAL, "instance %d has no nodes (offsets[%d]=%d, offsets[%d]=%d)", i, i, offsets[i], i + 1,
+                  offsets[i + 1]);
+  if (offsets[n_inst] != n_nodes)
+    return fail(RTN_EINVAL, "offsets[n_inst] = %d but n_nodes = %d", offsets[n_inst], n_nodes);
+  return RTN_OK;
+}
+
+extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const rtn_quad* quad, float dt,
+                                    int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes, const float* x,
+                                    const float* u, float* x_next, float* A, float* B, float* f_D, float* J_D,
+                                    uint8_t* status, void* stream) {
+  if (!quad) return fail(RTN_EINVAL, "quad is NULL");
+  if (!(dt > 0.f) || !std::isfinite(dt)) return fail(RTN_EINVAL, "dt must be positive and finite");
+  if (!(quad->mass > 0.f) || !(quad->Jx > 0.f) || !(quad->Jy > 0.f) || !(quad->Jz > 0.f))
+    return fail(RTN_EINVAL, "quad mass and inertia must be positive");
+  rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
+  if (s) return s;
+  if (model && prec != RTN_FP32 && prec != RTN_BF16 && prec != RTN_FP8)
+    return fail(RTN_EINVAL, "unknown precision %d", prec);
+  if (n_nodes == 0) return RTN_OK;
+  if (!x || !u) return fail(RTN_EINVAL, "x and u must be device pointers");
+  if (!x_next || !A || !B) return fail(RTN_EINVAL, "x_next, A and B must be device pointers");
+  Model* m = const_cast<Model*>(reinterpret_cast<const Model*>(model));
+  if (m && prec == RTN_FP8 && !m->calibrated)
+    return fail(RTN_EINVAL, "RTN_FP8 needs rtn_model_calibrate first");
+  hipStream_t st = (hipStream_t)stream;
+  QuadConst qc{quad->mass, quad->Jx, quad->Jy, quad->Jz, quad->arm, quad->c_tau, quad->g};
+  const float* fD_in = nullptr;
+  const float* JD_in = nullptr;
+  if (m) {
+    if ((s = m->ensure_workspace(n_nodes, 0, st))) return s;
+    float* y = f_D ? f_D : m->tmp;
+    float* J = J_D ? J_D : m->tmp + (size_t)n_nodes * kDout;
+    NetView v = m->view(prec);
+    HIP_TRY(launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, st));
+    HIP_TRY(launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, st));
+    fD_in = y;
+    JD_in = J;
+  } else {
+    if (f_D) HIP_TRY(hipMemsetAsync(f_D, 0, (size_t)n_nodes * kDout * 4, st));
+    if (J_D) HIP_TRY(hipMemsetAsync(J_D, 0, (size_t)n_nodes * kDout * kDin * 4, st));
+  }
+  HIP_TRY(launch_rk4_linearize(n_nodes, qc, dt, x, u, fD_in, JD_in, x_next, A, B, status, st));
+  return RTN_OK;
+}

@@ -1,0 +1,98 @@
+"""The C ABI library loads, exports every declared symbol, and validates arguments
+on the host before touching the GPU (these tests run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2203_07747_amd import _lib
+from paper_2203_07747_amd._lib import MlpDesc, Quad, load, RTN_OK, RTN_EINVAL, RTN_ENOTSUP
+from workload import QUAD
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rtn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtn_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("librtn.so not built")
+    return load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.rtn_version()
+
+
+def desc(L=2, W=64, act=0, d_in=14, d_out=6):
+    return MlpDesc(d_in, d_out, L, W, act)
+
+
+def test_param_count(lib):
+    n = ctypes.c_int64()
+    assert lib.rtn_param_count(ctypes.byref(desc(2, 64)), ctypes.byref(n)) == RTN_OK
+    assert n.value == 64 * 14 + 64 + 64 * 64 + 64 + 6 * 64 + 6  # 5510
+    assert lib.rtn_param_count(ctypes.byref(desc(4, 512)), ctypes.byref(n)) == RTN_OK
+    assert n.value == 798726
+    assert lib.rtn_param_count(ctypes.byref(desc(5, 512)), ctypes.byref(n)) == RTN_OK
+    assert n.value == 1061382
+
+
+@pytest.mark.parametrize("d,code", [
+    (desc(d_in=13), RTN_EINVAL), (desc(d_out=5), RTN_EINVAL), (desc(L=0), RTN_EINVAL),
+    (desc(L=17), RTN_EINVAL), (desc(act=7), RTN_EINVAL), (desc(W=96), RTN_ENOTSUP), (desc(W=0), RTN_EINVAL)])
+def test_bad_descriptor(lib, d, code):
+    n = ctypes.c_int64()
+    assert lib.rtn_param_count(ctypes.byref(d), ctypes.byref(n)) == code
+    assert len(lib.rtn_last_error()) > 0
+
+
+def call_linearize(lib, quad=True, dt=0.05, n_inst=1, offsets=None, n=0, prec=0, ptrs=False):
+    q = Quad(QUAD.mass, QUAD.Jx, QUAD.Jy, QUAD.Jz, QUAD.arm, QUAD.c_tau, QUAD.g)
+    off = None
+    if offsets is not None:
+        arr = np.asarray(offsets, dtype=np.int32)
+        off = arr.ctypes.data_as(ctypes.c_void_p)
+        call_linearize._keep = arr
+    p = ctypes.c_void_p(16) if ptrs else None  # never dereferenced: validation fails first
+    return lib.rtn_linearize(None, prec, ctypes.byref(q) if quad else None, ctypes.c_float(dt), n_inst, off, n,
+                             p, p, p, p, p, None, None, None, None)
+
+
+def test_linearize_validation(lib):
+    assert call_linearize(lib, quad=False) == RTN_EINVAL
+    assert call_linearize(lib, dt=0.0) == RTN_EINVAL
+    assert call_linearize(lib, dt=float("nan")) == RTN_EINVAL
+    assert call_linearize(lib, n=-1) == RTN_EINVAL
+    assert call_linearize(lib, n_inst=0) == RTN_EINVAL
+    assert call_linearize(lib, n_inst=2, offsets=None, n=4) == RTN_EINVAL        # NULL offsets need n_inst == 1
+    assert call_linearize(lib, n_inst=2, offsets=[1, 2, 4], n=4, ptrs=True) == RTN_EINVAL  # offsets[0] != 0
+    assert call_linearize(lib, n_inst=2, offsets=[0, 2, 2], n=2, ptrs=True) == RTN_EINVAL  # empty instance
+    assert call_linearize(lib, n_inst=2, offsets=[0, 2, 5], n=4, ptrs=True) == RTN_EINVAL  # end != n_nodes
+    assert call_linearize(lib, n=5) == RTN_EINVAL                                 # NULL arrays
+    assert b"device pointers" in lib.rtn_last_error()
+    # an empty batch is valid and does no work
+    assert call_linearize(lib, n=0) == RTN_OK
+    assert call_linearize(lib, n_inst=1, offsets=[0, 0], n=0) == RTN_EINVAL       # an instance must have a node
+
+
+def test_model_calls_reject_null(lib):
+    assert lib.rtn_model_create(ctypes.byref(desc()), None, ctypes.byref(ctypes.c_void_p())) == RTN_EINVAL
+    assert lib.rtn_model_destroy(None) == RTN_OK
+    assert lib.rtn_model_set_params(None, None) == RTN_EINVAL
+    assert lib.rtn_model_calibrate(None, 4, None, None, None) == RTN_EINVAL

@@ -1,0 +1,205 @@
+"""GPU parity of rtn_linearize against the FP64 oracle (element by element).
+
+Error measure per node and output: e = |X_gpu - X_oracle|_F / |X_oracle|_F; the
+bound is on the maximum over nodes.  Bounds: FP32 1e-5, BF16 1e-2, FP8 5e-2 on
+x_{k+1}, A_k, B_k.  The network parts f_D-bar and J_D are also compared, against
+the exact oracle and, for the reduced-precision paths, against the oracle's
+evaluation with the same operand roundings.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from workload import (CONFIGS, QUAD, SEED_CALIB, config_workload, sample_nodes, xavier_params,
+                      offsets_from_horizons, sample_horizons)
+from oracle.mlp import MLP, pack_input
+from oracle.rk4 import linearize_affine
+from oracle.quant import emulated_jacobian, calibrate_scales
+
+pytestmark = pytest.mark.gpu
+DT = 0.05
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-30)
+
+
+def gpu_linearize(torch, x, u, Ws=None, bs=None, prec="fp32", act="silu", offsets=None, model=None, calib=None,
+                  want_status=False):
+    import paper_2203_07747_amd as rtn
+    print(f"[gpu] linearize n={x.shape[0]} prec={prec} "
+          f"L={len(Ws) - 1 if Ws else '-'} H={Ws[0].shape[0] if Ws else '-'}", flush=True)
+    own = False
+    if model is None and Ws is not None:
+        model, own = rtn.Model(Ws, bs, act), True
+    if calib is not None:
+        model.calibrate(torch.from_numpy(calib[0]).cuda(), torch.from_numpy(calib[1]).cuda())
+    out = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), model, prec, DT,
+                        offsets=offsets, want_status=want_status)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if own:
+        model.close()
+    return res
+
+
+def check_against(res, ref, tol, idx=None, parts=("x_next", "A", "B")):
+    names = ("x_next", "A", "B", "f_D", "J_D")
+    errs = {}
+    for name, r in zip(names, ref):
+        g = res[name] if idx is None else res[name][idx]
+        errs[name] = float(rel(g, r).max())
+    print("  max rel err:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for p in parts:
+        assert errs[p] <= tol, (p, errs[p], tol)
+    return errs
+
+
+@pytest.mark.parametrize("key", ["c1", "c2"])
+def test_fp32_configs_match_oracle(torch, key):
+    cfg, off, x, u, Ws, bs = config_workload(key)
+    res = gpu_linearize(torch, x, u, Ws, bs, "fp32", offsets=off)
+    ref = linearize_affine(x, u, MLP(Ws, bs), cfg.dt)
+    errs = check_against(res, ref, 1e-5)
+    assert errs["f_D"] < 1e-5 and errs["J_D"] < 1e-5
+
+
+@pytest.mark.parametrize("H,L,n", [(64, 2, 1), (64, 3, 300), (128, 2, 257), (256, 3, 129), (512, 2, 97),
+                                   (1024, 2, 67), (512, 1, 33)])
+def test_fp32_widths_and_ragged_tails(torch, H, L, n):
+    """Sizes span several row blocks of both kernels and end in a partial block."""
+    Ws, bs = xavier_params(L, H, seed=H + L)
+    bs = [np.random.default_rng(7).normal(size=b.shape).astype(np.float32) * 0.1 for b in bs]
+    x, u = sample_nodes(n, seed=n)
+    res = gpu_linearize(torch, x, u, Ws, bs, "fp32")
+    ref = linearize_affine(x, u, MLP(Ws, bs), DT)
+    errs = check_against(res, ref, 1e-5)
+    assert errs["J_D"] < 2e-5
+
+
+def test_identity_network_jacobian_is_constant(torch):
+    Ws, bs = xavier_params(3, 128, seed=3)
+    x, u = sample_nodes(50, seed=5)
+    res = gpu_linearize(torch, x, u, Ws, bs, "fp32", act="identity")
+    prod = Ws[3].astype(np.float64) @ Ws[2] @ Ws[1] @ Ws[0]
+    np.testing.assert_allclose(res["J_D"], np.broadcast_to(prod, res["J_D"].shape), rtol=1e-4, atol=1e-6)
+    ref = linearize_affine(x, u, MLP(Ws, bs, "identity"), DT)
+    check_against(res, ref, 1e-5)
+
+
+def test_nominal_only(torch):
+    x, u = sample_nodes(1000, seed=9)
+    res = gpu_linearize(torch, x, u)
+    ref = linearize_affine(x, u, None, DT)
+    check_against(res, ref, 1e-5, parts=("x_next", "A", "B"))
+    assert np.all(res["f_D"] == 0) and np.all(res["J_D"] == 0)
+
+
+def test_empty_batch(torch):
+    import paper_2203_07747_amd as rtn
+    Ws, bs = xavier_params(2, 64)
+    m = rtn.Model(Ws, bs)
+    z = torch.zeros((0, 13), device="cuda"), torch.zeros((0, 4), device="cuda")
+    out = rtn.linearize(z[0], z[1], m, "bf16")
+    torch.cuda.synchronize()
+    assert out["A"].shape == (0, 13, 13)
+
+
+def test_repeat_calls_bit_identical_and_offsets_irrelevant(torch):
+    Ws, bs = xavier_params(3, 512)
+    hz = sample_horizons(40, 10, 50)
+    off = offsets_from_horizons(hz)
+    x, u = sample_nodes(int(off[-1]), seed=3)
+    a = gpu_linearize(torch, x, u, Ws, bs, "bf16", offsets=off)
+    b = gpu_linearize(torch, x, u, Ws, bs, "bf16")
+    for k in ("x_next", "A", "B", "f_D", "J_D"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_status_flags(torch):
+    Ws, bs = xavier_params(2, 64)
+    x, u = sample_nodes(40, seed=4)
+    x[5, 7] = np.nan
+    res = gpu_linearize(torch, x, u, Ws, bs, "fp32", want_status=True)
+    st = res["status"]
+    assert st[5] & 2 and st[5] & 1  # NaN input poisons the network output and the step
+    assert np.all(st[np.arange(40) != 5] == 0)
+    Ws[1][3, 4] = np.nan
+    res = gpu_linearize(torch, sample_nodes(8)[0], sample_nodes(8)[1], Ws, bs, "fp32", want_status=True)
+    assert np.all(res["status"] & 1)
+
+
+def test_bf16_matches_emulation_and_oracle(torch):
+    Ws, bs = xavier_params(5, 512, seed=0)
+    x, u = sample_nodes(2000, seed=1)
+    res = gpu_linearize(torch, x, u, Ws, bs, "bf16")
+    net = MLP(Ws, bs)
+    ref = linearize_affine(x, u, net, DT)
+    check_against(res, ref, 1e-2)
+    ye, Je = emulated_jacobian(net, pack_input(x, u), "bf16")
+    e_y, e_J = rel(res["f_D"], ye).max(), rel(res["J_D"], Je).max()
+    print(f"  vs bf16 emulation: f_D {e_y:.2e} J_D {e_J:.2e}")
+    assert e_y < 2e-3 and e_J < 2e-3
+
+
+def test_c3_full_size_sampled(torch):
+    """The benchmarked workload (4096 instances, ragged horizons, 14-5x512-6 bf16) at full size;
+    the oracle checks a seeded sample of nodes."""
+    cfg, off, x, u, Ws, bs = config_workload("c3")
+    res = gpu_linearize(torch, x, u, Ws, bs, "bf16", offsets=off)
+    n = x.shape[0]
+    idx = np.sort(np.random.default_rng(11).choice(n, 1500, replace=False))
+    idx = np.unique(np.concatenate([idx, [0, n - 1]]))
+    ref = linearize_affine(x[idx], u[idx], MLP(Ws, bs), cfg.dt)
+    check_against(res, ref, 1e-2, idx=idx)
+    for k in ("x_next", "A", "B"):
+        assert np.all(np.isfinite(res[k]))
+
+
+def test_fp8_matches_emulation_and_oracle(torch):
+    Ws, bs = xavier_params(4, 1024, seed=0)
+    xc, uc = sample_nodes(8192, seed=SEED_CALIB)
+    x, u = sample_nodes(600, seed=1)
+    res = gpu_linearize(torch, x, u, Ws, bs, "fp8", calib=(xc, uc))
+    net = MLP(Ws, bs)
+    ref = linearize_affine(x, u, net, DT)
+    check_against(res, ref, 5e-2)
+    sc = calibrate_scales(net, pack_input(xc, uc))
+    ye, Je = emulated_jacobian(net, pack_input(x, u), "fp8", sc)
+    e_y, e_J = rel(res["f_D"], ye).max(), rel(res["J_D"], Je).max()
+    print(f"  vs fp8 emulation: f_D {e_y:.2e} J_D {e_J:.2e}")
+    assert e_y < 2e-2 and e_J < 2e-2
+
+
+def test_fp8_calibration_scales_match_oracle(torch):
+    import paper_2203_07747_amd as rtn
+    Ws, bs = xavier_params(3, 256, seed=2)
+    xc, uc = sample_nodes(4096, seed=SEED_CALIB)
+    m = rtn.Model(Ws, bs)
+    m.calibrate(torch.from_numpy(xc).cuda(), torch.from_numpy(uc).cuda())
+    got = m.scales()
+    sc = calibrate_scales(MLP(Ws, bs), pack_input(xc, uc))
+    want = np.array(sc["w"] + sc["a"] + sc["g"])
+    np.testing.assert_allclose(got, want, rtol=1e-5)
+    m.close()
+
+
+def test_c4_fp8_full_size_sampled(torch):
+    cfg, off, x, u, Ws, bs = config_workload("c4")
+    xc, uc = sample_nodes(65536, seed=SEED_CALIB)
+    res = gpu_linearize(torch, x, u, Ws, bs, "fp8", offsets=off, calib=(xc, uc))
+    n = x.shape[0]
+    idx = np.unique(np.concatenate([np.random.default_rng(12).choice(n, 400, replace=False), [0, n - 1]]))
+    ref = linearize_affine(x[idx], u[idx], MLP(Ws, bs), cfg.dt)
+    check_against(res, ref, 5e-2, idx=idx)

@@ -118,3 +118,18 @@ def test_round_e4m3_matches_torch():
     ref = torch.from_numpy(v).to(torch.float8_e4m3fn).to(torch.float64).numpy()
     np.testing.assert_array_equal(round_e4m3(v), ref)
     assert round_e4m3(np.array([1000.0, -500.0])).tolist() == [448.0, -448.0]
+
+
+def test_emulation_exact_when_everything_is_representable():
+    """With small-integer weights and inputs every rounding is exact, so the
+    reduced-precision evaluation must reproduce the exact chain rule bit for bit."""
+    from oracle.quant import emulated_jacobian
+    rng = np.random.default_rng(4)
+    Ws = [rng.integers(-1, 2, size=s).astype(np.float64) for s in [(8, 14), (8, 8), (6, 8)]]
+    bs = [np.zeros(8), np.zeros(8), np.zeros(6)]
+    net = MLP(Ws, bs, act="identity")
+    z = rng.integers(-3, 4, size=(5, 14)).astype(np.float64)
+    y, J = net.jacobian(z)
+    ye, Je = emulated_jacobian(net, z, "bf16")
+    np.testing.assert_array_equal(ye, y)
+    np.testing.assert_array_equal(Je, J)

@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the Real-time Neural MPC linearisation path on one MI355X.
+
+A step is one rtn_linearize call over the whole batch of one workload: pack ->
+network forward -> reverse-mode Jacobian -> RK4 with sensitivities -> stores of
+x_{k+1}, A_k, B_k (and f_D, J_D) for every node of every instance.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+Default workload: 4096 MPC instances with horizons N_i ~ U{10..50}, residual
+network 14-5x512-6 in bf16 (fp32 accumulation), dt = 0.05 s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from workload import CONFIGS, SEED_CALIB, config_workload, sample_nodes  # noqa: E402
+
+METRIC = "node linearisations/sec (f, A_k, B_k) BF16/FP8 vs FP32 at stated err vs FP64"
+# MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_node(L: int, H: int, d_in: int = 14, d_out: int = 6):
+    """Algorithmic flops: one forward pass and one reverse-mode Jacobian per node."""
+    W = d_in * H + (L - 1) * H * H + H * d_out
+    fwd = 2 * W
+    rev = 2 * d_out * ((L - 1) * H * H + H * d_in)
+    return fwd, rev
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--config", default="c3", choices=sorted(CONFIGS))
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-compare", action="store_true", help="skip the other-precision comparison runs")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def time_steps(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall / steps * 1e3
+
+
+def cpu_baseline(cfg, x, u, Ws, bs, gpu_out, seconds):
+    """The FP64 oracle, as it stands, on a bounded prefix of the same nodes; also the
+    error of the GPU outputs on that prefix against it."""
+    import threadpoolctl
+    from oracle.mlp import MLP
+    from oracle.rk4 import linearize_affine
+    net = MLP(Ws, bs)
+    n_sample = min(2048, x.shape[0])
+    done, t0 = 0, time.perf_counter()
+    ref = None
+    while True:
+        r = linearize_affine(x[:n_sample], u[:n_sample], net, cfg.dt)
+        ref = r if ref is None else ref
+        done += n_sample
+        if time.perf_counter() - t0 >= seconds:
+            break
+    elapsed = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    errs = {}
+    for name, r in zip(("x_next", "A", "B", "f_D", "J_D"), ref):
+        g = gpu_out[name][:n_sample].reshape(n_sample, -1).astype(np.float64)
+        rr = r.reshape(n_sample, -1)
+        e = np.linalg.norm(g - rr, axis=1) / np.maximum(np.linalg.norm(rr, axis=1), 1e-30)
+        errs[name] = {"max": float(e.max()), "p999": float(np.quantile(e, 0.999))}
+    cpu = {"value": done / elapsed, "unit": "nodes/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"first {n_sample} nodes of the workload, fp64 NumPy oracle, repeated for "
+                     f"{elapsed:.1f} s ({done} node linearisations)"}
+    return cpu, errs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(nodes are independent, so G GPUs would each take a contiguous range of instances)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2203_07747_amd as rtn
+
+    torch.cuda.set_device(0)
+    cfg, off, x, u, Ws, bs = config_workload(args.config)
+    n = x.shape[0]
+    prec = cfg.precision
+    L, H = cfg.n_hidden, cfg.width
+    model = rtn.Model(Ws, bs)
+    xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
+    calibrated = False
+
+    def ensure_calibrated():
+        nonlocal calibrated
+        if not calibrated:
+            xc, uc = sample_nodes(65536, seed=SEED_CALIB)
+            model.calibrate(torch.from_numpy(xc).cuda(), torch.from_numpy(uc).cuda())
+            calibrated = True
+
+    if prec == "fp8":
+        ensure_calibrated()
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def step(p=prec):
+        rtn.linearize(xt, ut, model, p, cfg.dt, offsets=off, out=out, stream=stream)
+
+    ms, wall_ms = time_steps(torch, step, args.steps, args.warmup, stream)
+    value = n / (ms * 1e-3)
+
+    # per-kernel durations from events bracketing each kernel on the launching stream
+    rtn.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kern = rtn.profile_collect()
+    rtn.profile_enable(False)
+    gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
+
+    f_fwd, f_rev = flops_per_node(L, H)
+    rev_ms = kern.get("mlp_reverse_chain", {}).get("avg_ms", float("nan"))
+    fwd_ms = kern.get("mlp_forward_chain", {}).get("avg_ms", float("nan"))
+    rk4_ms = kern.get("rk4_linearize", {}).get("avg_ms", float("nan"))
+    achieved = n * f_rev / (rev_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    result = {
+        "metric": METRIC, "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": cfg.name, "n_inst": int(len(off) - 1), "n_nodes": int(n),
+                   "hidden_layers": L, "width": H, "dt": cfg.dt},
+        "roofline": {"bound": "mfma", "kernel": "mlp_reverse_chain", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "algorithmic_flops_per_launch": n * f_rev, "avg_launch_ms": rev_ms},
+        "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms},
+        "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,
+        "host_wall_ms_per_step": wall_ms,
+    }
+    if not args.no_compare:
+        cmp = {}
+        for p in ("fp32", "bf16", "fp8"):
+            if p == prec:
+                continue
+            if p == "fp8":
+                ensure_calibrated()
+            o2 = {}
+            def s2(pp=p, oo=o2):
+                rtn.linearize(xt, ut, model, pp, cfg.dt, offsets=off, out=oo, stream=stream)
+            k2 = max(3, args.steps // 5)
+            m2, _ = time_steps(torch, s2, k2, 2, stream)
+            cmp[p] = {"value": n / (m2 * 1e-3), "ms_per_step": m2, "steps": k2,
+                      "mfma_frac": n * (f_fwd + f_rev) / (m2 * 1e-3) / 1e12 / PEAK_TFLOPS[p]}
+        result["other_precisions_same_workload"] = cmp
+    if not args.no_cpu:
+        cpu, errs = cpu_baseline(cfg, x, u, Ws, bs, gpu_out, args.cpu_seconds)
+        result["cpu_baseline"] = cpu
+        result["err_vs_fp64"] = errs
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -209,6 +209,22 @@ rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch,
 rtn_status rtn_model_get_adam(rtn_model* model, float* m_host, float* v_host, int64_t* step);
 rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float* v_host, int64_t step);
 
+/* Kernel timing (tracing).  When enabled, every kernel the library launches is
+ * bracketed by a pair of HIP events recorded on the call's stream (a few
+ * microseconds of overhead per launch; leave it off for production timing).
+ * rtn_profile_read waits for the recorded events, aggregates them per kernel
+ * (name, number of launches, summed event time in milliseconds), writes up to
+ * max_entries records to out (host, nullable), sets *n_entries to the number of
+ * distinct kernels and clears the records.  Synchronous. */
+typedef struct {
+    char name[48];
+    int32_t calls;
+    double total_ms;
+} rtn_kernel_time;
+
+rtn_status rtn_profile_enable(int32_t on);
+rtn_status rtn_profile_read(rtn_kernel_time* out, int32_t max_entries, int32_t* n_entries);
+
 #ifdef __cplusplus
 }
 #endif

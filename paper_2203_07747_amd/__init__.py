@@ -15,11 +15,28 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "linearize", "riccati", "version", "quad_struct", "PREC"]
+__all__ = ["Model", "linearize", "riccati", "version", "quad_struct", "PREC", "profile_enable", "profile_collect"]
 
 
 def version() -> str:
     return load().rtn_version().decode()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel with HIP events on its stream (see rtn_profile_enable)."""
+    check(load().rtn_profile_enable(1 if on else 0), "rtn_profile_enable")
+
+
+def profile_collect() -> Dict[str, Dict[str, float]]:
+    buf = (_lib.KernelTime * 64)()
+    n = ctypes.c_int32()
+    check(load().rtn_profile_read(buf, 64, ctypes.byref(n)), "rtn_profile_read")
+    out = {}
+    for i in range(min(n.value, 64)):
+        r = buf[i]
+        out[r.name.decode()] = {"calls": r.calls, "total_ms": r.total_ms,
+                                "avg_ms": r.total_ms / max(r.calls, 1)}
+    return out
 
 
 def _torch():

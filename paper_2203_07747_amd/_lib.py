@@ -28,6 +28,10 @@ class Quad(ctypes.Structure):
                 ("c_tau", c_float), ("g", c_float)]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("calls", c_int32), ("total_ms", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); every function returns rtn_status unless stated
 SIGNATURES = {
     "rtn_version": (ctypes.c_char_p, []),
@@ -54,6 +58,8 @@ SIGNATURES = {
                                  c_float, c_float, c_void_p, c_void_p]),
     "rtn_model_get_adam": (c_int32, [c_void_p, c_void_p, c_void_p, P(c_int64)]),
     "rtn_model_set_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64]),
+    "rtn_profile_enable": (c_int32, [c_int32]),
+    "rtn_profile_read": (c_int32, [c_void_p, c_int32, P(c_int32)]),
 }
 
 _lib = None

@@ -18,6 +18,7 @@ struct NetView {
   const void* rw[16];
   const float* bias[17];
   const float* w_out;   // fp32 W_{L+1} [6][H]
+  const float* w_out_s; // the same, each row in stash order (element stash_pos(k) holds column k)
   const float* wscale;  // fp8: dequantisation scale of W_1..W_{L+1} (L+1)
   const float* ascale;  // fp8: scale of the forward operands z_0, h_1..h_L (L+1)
   const float* gscale;  // fp8: scale of the reverse operands G_1..G_L (L)
@@ -36,6 +37,7 @@ hipError_t launch_mlp_forward(int prec, int H, const NetView& net, int n, const 
 hipError_t launch_mlp_reverse(int prec, int H, const NetView& net, int n, const void* stash, float* J, float* amax,
                               hipStream_t st);
 int stash_elem_bytes(int prec);
+hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st);
 
 struct QuadConst {
   float mass, Jx, Jy, Jz, arm, c_tau, g;

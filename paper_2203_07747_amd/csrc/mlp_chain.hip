@@ -28,14 +28,17 @@
 namespace rtn {
 
 // Rows per workgroup and waves per workgroup for a (precision, width) pair.
-// Limits: the B operand of R rows x H features must fit in LDS, and each wave's
-// accumulators (H/32/NW M-tiles x R/32 row tiles x 16 floats) must stay <= 128
-// registers.
+// Limits: the B operand of R rows x H features (plus the staged activation
+// derivatives of the reverse sweep) must fit in the 160 KB of LDS, and each
+// wave's accumulators (H/32/NW M-tiles x R/32 row tiles x 16 floats) must fit its
+// registers: <= 128 with two waves per SIMD (8 waves), <= 192 with one wave per
+// SIMD (4 waves), where the accumulators live in AGPRs.
 template <int P, int H> struct ChainShape {
-  static constexpr int NW = H >= 256 ? 8 : H / 32;
+  static constexpr bool ONE_PER_SIMD = P != P_FP32 && H == 512;
+  static constexpr int NW = ONE_PER_SIMD ? 4 : (H >= 256 ? 8 : H / 32);
   static constexpr int R = P == P_FP32 ? (H <= 256 ? 128 : (H == 512 ? 64 : 32))
                          : P == P_BF16 ? (H <= 256 ? 128 : (H == 512 ? 96 : 64))
-                                       : (H <= 512 ? 128 : 64);
+                                       : (H <= 256 ? 128 : (H == 512 ? 96 : 64));
 };
 
 template <int P, int H, int R, int NW> struct Chain {
@@ -52,8 +55,14 @@ template <int P, int H, int R, int NW> struct Chain {
   static constexpr int B_BYTES = R * H * (int)sizeof(elem);
   static constexpr int PART_BYTES = NW * R * 16 * 4;
   static constexpr int LDS_BYTES = B_BYTES > PART_BYTES ? B_BYTES : PART_BYTES;
+  // reverse sweep: the activation derivatives of the nodes a row block touches
+  static constexpr int SP_NODES = R % 6 == 0 ? R / 6 : R / 6 + 2;
+  static constexpr int SP_ELEM = P == P_FP32 ? 4 : 2;
+  static constexpr int SP_BYTES = SP_NODES * H * SP_ELEM;
+  static constexpr int SP_CHUNKS_PER_THREAD = (SP_BYTES / 16 + NW * kWave - 1) / (NW * kWave);
+  static constexpr int REV_LDS_BYTES = LDS_BYTES + SP_BYTES;
   static_assert(MT % NW == 0, "width must split evenly over the waves");
-  static_assert(MTW * RT * 16 <= 128, "accumulator budget");
+  static_assert(MTW * RT * 16 <= (NW <= 4 ? 192 : 128), "accumulator budget");
 
   // LDS element index of (row tile, K-step, lane, slot-in-step) for an operand with KS K-steps.
   __device__ static inline int lidx(int rt, int s, int lane, int KS) { return ((rt * KS + s) * kWave + lane) * E; }
@@ -62,41 +71,77 @@ template <int P, int H, int R, int NW> struct Chain {
     return *reinterpret_cast<const frag*>(lds + lidx(rt, s, lane, KS));
   }
 
-  // acc[i][r] = sum_s A(mt0+i, s) * B(r, s) over K-steps [s0, s1), NMT M-tiles.
-  template <int NMT>
-  __device__ static inline void gemm(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int KS, int mt0,
-                                     int s0, int s1, const elem* lds, int lane) {
+  // acc[i][r] = sum over NSTEPS K-steps from s0 of A(mt0+i, s) * B(r, s), NMT M-tiles.
+  // Weight fragments stream through a PD-deep register ring (loads are issued PD steps
+  // ahead of their use, hiding L2 latency); LDS operand fragments are double-buffered.
+  template <int NMT, int NSTEPS>
+  __device__ static inline void gemm(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int MTALL, int KS,
+                                     int mt0, int s0, int rot, const elem* lds, int lane) {
+    // ring depth: up to 4 steps, at most 128 (two waves per SIMD) or 256 (one wave
+    // per SIMD) bytes of weight fragments per lane
+    constexpr int PD0 = (NW <= 4 ? 256 : 128) / (NMT * (int)sizeof(frag));
+    constexpr int PD1 = PD0 < 1 ? 1 : (PD0 > 4 ? 4 : PD0);
+    constexpr int PD = NSTEPS < PD1 ? NSTEPS : PD1;
+    static_assert(NSTEPS % PD == 0, "K-steps must be a multiple of the prefetch depth");
+    static_assert((NSTEPS & (NSTEPS - 1)) == 0, "K-steps must be a power of two");
+    // K-step visited at position s: the loop starts at a per-block rotation so that
+    // workgroups running in lock-step read different parts of the weight matrix
+    auto kstep = [&](int s) { return s0 + ((s + rot) & (NSTEPS - 1)); };
+    auto wfrag = [&](int s, int i) { return Wp[((size_t)kstep(s) * MTALL + mt0 + i) * kWave + lane]; };
 #pragma unroll
     for (int i = 0; i < NMT; ++i)
 #pragma unroll
       for (int r = 0; r < RT; ++r) acc[i][r] = f32x16{};
-    if (s0 >= s1) return;
-    frag a[NMT];
+    frag a[PD][NMT];
 #pragma unroll
-    for (int i = 0; i < NMT; ++i) a[i] = Wp[((mt0 + i) * KS + s0) * kWave + lane];
-    for (int s = s0; s < s1; ++s) {
-      frag an[NMT];
-      const int sn = s + 1 < s1 ? s + 1 : s;
+    for (int d = 0; d < PD; ++d)
 #pragma unroll
-      for (int i = 0; i < NMT; ++i) an[i] = Wp[((mt0 + i) * KS + sn) * kWave + lane];
-      frag b[RT];
+      for (int i = 0; i < NMT; ++i) a[d][i] = wfrag(d, i);
+    frag b[RT];
 #pragma unroll
-      for (int r = 0; r < RT; ++r) b[r] = lds_frag(lds, r, s, lane, KS);
+    for (int r = 0; r < RT; ++r) b[r] = lds_frag(lds, r, kstep(0), lane, KS);
+    // steady state: every step prefetches the weights PD steps ahead
+    for (int g = 0; g < NSTEPS - PD; g += PD) {
+#pragma unroll
+      for (int d = 0; d < PD; ++d) {
+        const int s = g + d;
+        frag bn[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) bn[r] = lds_frag(lds, r, kstep(s + 1), lane, KS);
+#pragma unroll
+        for (int i = 0; i < NMT; ++i)
+#pragma unroll
+          for (int r = 0; r < RT; ++r) acc[i][r] = M::mma(a[d][i], b[r], acc[i][r]);
+#pragma unroll
+        for (int i = 0; i < NMT; ++i) a[d][i] = wfrag(s + PD, i);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) b[r] = bn[r];
+        // keep each step's loads where they are issued: PD steps ahead of their use
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // drain: the last PD steps
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int s = NSTEPS - PD + d;
+      frag bn[RT];
+      if (d + 1 < PD) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) bn[r] = lds_frag(lds, r, kstep(s + 1), lane, KS);
+      }
 #pragma unroll
       for (int i = 0; i < NMT; ++i)
 #pragma unroll
-        for (int r = 0; r < RT; ++r) acc[i][r] = M::mma(a[i], b[r], acc[i][r]);
+        for (int r = 0; r < RT; ++r) acc[i][r] = M::mma(a[d][i], b[r], acc[i][r]);
+      if (d + 1 < PD) {
 #pragma unroll
-      for (int i = 0; i < NMT; ++i) a[i] = an[i];
+        for (int r = 0; r < RT; ++r) b[r] = bn[r];
+      }
     }
   }
 
-  // K-step range of wave w when a narrow (one M-tile) layer splits its K over the waves.
-  __device__ static inline void split_k(int w, int* s0, int* s1) {
-    constexpr int per = (KS_H + NW - 1) / NW;
-    *s0 = w * per < KS_H ? w * per : KS_H;
-    *s1 = *s0 + per < KS_H ? *s0 + per : KS_H;
-  }
+  // K-steps per wave when a narrow (one M-tile) layer splits its K over the waves.
+  static constexpr int SPLIT = (KS_H + NW - 1) / NW;
 
   // Store 16 accumulator-ordered values of (row tile rt, M-tile mt) as operand slots
   // q = 16*mt .. 16*mt+15 of the next layer (K-steps over width H).
@@ -204,7 +249,12 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
     for (int layer = 0; layer < net.L; ++layer) {
       const int KS = layer == 0 ? C::KS_1 : C::KS_H;
       f32x16 acc[C::MTW][C::RT];
-      C::template gemm<C::MTW>(acc, reinterpret_cast<const frag*>(net.fw[layer]), KS, wave * C::MTW, 0, KS, lds, lane);
+      if (layer == 0)
+        C::template gemm<C::MTW, C::KS_1>(acc, reinterpret_cast<const frag*>(net.fw[0]), C::MT, C::KS_1, wave * C::MTW,
+                                          0, blk, lds, lane);
+      else
+        C::template gemm<C::MTW, C::KS_H>(acc, reinterpret_cast<const frag*>(net.fw[layer]), C::MT, C::KS_H,
+                                          wave * C::MTW, 0, blk, lds, lane);
       __syncthreads();
       const float scale = P == P_FP8 ? dq[layer] * net.ascale[layer] : 1.f;
       const float inv_next = P == P_FP8 ? 1.f / net.ascale[layer + 1] : 1.f;
@@ -245,9 +295,11 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
     // output layer y = W_{L+1} h_L + b: one 32-row M-tile (6 used), K split over the waves
     {
       f32x16 acc[1][C::RT];
-      int s0, s1;
-      C::split_k(wave, &s0, &s1);
-      C::template gemm<1>(acc, reinterpret_cast<const frag*>(net.fw[net.L]), C::KS_H, 0, s0, s1, lds, lane);
+      const int s0 = wave * C::SPLIT;
+      if (s0 < C::KS_H)
+        C::template gemm<1, C::SPLIT>(acc, reinterpret_cast<const frag*>(net.fw[net.L]), 1, C::KS_H, 0, s0, 0, lds, lane);
+      else
+        for (int r = 0; r < C::RT; ++r) acc[0][r] = f32x16{};
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < C::RT; ++r)
@@ -268,6 +320,12 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
 
 // ---------------------------------------------------------------------------
 // Reverse (adjoint) chain: 6 rows per node; J_D[node][j][c] for the 14 inputs.
+//
+// The activation derivatives a row block needs in a layer's epilogue are the rows
+// of its (at most R/6 + 2) nodes, contiguous in the stash.  They are fetched with
+// 16-byte loads issued before the layer's K-loop (so their latency hides behind
+// the matrix work) and parked in LDS when the loop ends; the next block's
+// first-layer rows are fetched during the current block's last K-loop.
 template <int P, int H>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H>::NW * kWave)))
 mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict__ stash,
@@ -277,30 +335,64 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
   using elem = typename C::elem;
   using frag = typename C::frag;
   using S = typename StashT<P>::type;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[C::LDS_BYTES];
+  constexpr int NT = NW * kWave;
+  constexpr int CH = C::SP_CHUNKS_PER_THREAD;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[C::REV_LDS_BYTES];
   elem* lds = reinterpret_cast<elem*>(smem);
   float* part = reinterpret_cast<float*>(smem);
+  S* sp_lds = reinterpret_cast<S*>(smem + C::LDS_BYTES);
+  i32x4* sp_lds4 = reinterpret_cast<i32x4*>(smem + C::LDS_BYTES);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
   const int nrows = 6 * n;
   const int nblocks = (nrows + R - 1) / R;
   const int L = net.L;
+  const size_t layer_stride = (size_t)n * H;
+
+  i32x4 sp_reg[CH];
+  // issue the loads of stash layer `layer` for the nodes of the block starting at row r0
+  auto sp_fetch = [&](int layer, int r0) {
+    const int node0 = r0 / 6;
+    const int node1 = min(n, (min(r0 + R, nrows) + 5) / 6);
+    const int nchunks = (node1 - node0) * H * (int)sizeof(S) / 16;
+    const i32x4* src = reinterpret_cast<const i32x4*>(stash + (size_t)layer * layer_stride + (size_t)node0 * H);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int idx = tid + c * NT;
+      if (idx < nchunks) sp_reg[c] = __builtin_nontemporal_load(src + idx);
+    }
+  };
+  auto sp_park = [&]() {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int idx = tid + c * NT;
+      if (idx < C::SP_BYTES / 16) sp_lds4[idx] = sp_reg[c];
+    }
+  };
+
+  if (blockIdx.x < nblocks) sp_fetch(L - 1, blockIdx.x * R);
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int row0 = blk * R;
+    const int node0 = row0 / 6;
+    sp_park();
+    __syncthreads();
     // G_L[row][k] = W_{L+1}[row % 6][k] * act'(a_L)[row / 6][k]
     {
-      const S* spL = stash + (size_t)(L - 1) * n * H;
       const float inv = P == P_FP8 ? 1.f / net.gscale[L - 1] : 1.f;
-      for (int it = tid; it < C::RT * C::KS_H * kWave; it += NW * kWave) {
+      for (int it = tid; it < C::RT * C::KS_H * kWave; it += NT) {
         const int l = it % kWave, s = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
         const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
+        const bool live = row < nrows;
+        const int node = live ? row / 6 : node0, j6 = live ? row - 6 * node : 0;
+        const S* spn = sp_lds + (node - node0) * H;
+        const float* wo = net.w_out_s + j6 * H;
         float v[C::E];
-        const int node = row / 6, j6 = row - 6 * (row / 6);
 #pragma unroll
         for (int j = 0; j < C::E; ++j) {
-          const int k = slot_feature(s * C::E + j, gg);
-          v[j] = row < nrows ? net.w_out[j6 * H + k] * from_stash(spL[(size_t)node * H + stash_pos(k)]) : 0.f;
-          if (amax && row < nrows) atomic_amax(&amax[L - 1], v[j]);
+          const int q = s * C::E + j;
+          const int pos = 32 * (q >> 4) + gg * 16 + (q & 15);  // stash order of slot q
+          v[j] = live ? wo[pos] * from_stash(spn[pos]) : 0.f;
+          if (amax && live) atomic_amax(&amax[L - 1], v[j]);
         }
         C::put_slots(lds, rt, s, l, C::KS_H, v, inv);
       }
@@ -308,20 +400,22 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     __syncthreads();
 
     for (int layer = L - 1; layer >= 1; --layer) {  // weights W_{layer+1}^T, stash of h_layer
+      sp_fetch(layer - 1, row0);
       f32x16 acc[C::MTW][C::RT];
-      C::template gemm<C::MTW>(acc, reinterpret_cast<const frag*>(net.rw[layer]), C::KS_H, wave * C::MTW, 0, C::KS_H, lds, lane);
+      C::template gemm<C::MTW, C::KS_H>(acc, reinterpret_cast<const frag*>(net.rw[layer]), C::MT, C::KS_H, wave * C::MTW,
+                                        0, blk, lds, lane);
+      sp_park();
       __syncthreads();
       const float scale = P == P_FP8 ? net.wscale[layer] * net.gscale[layer] : 1.f;
       const float inv_next = P == P_FP8 ? 1.f / net.gscale[layer - 1] : 1.f;
-      const S* sp = stash + (size_t)(layer - 1) * n * H;
 #pragma unroll
       for (int i = 0; i < C::MTW; ++i) {
         const int mt = wave * C::MTW + i;
 #pragma unroll
         for (int r = 0; r < C::RT; ++r) {
           const int row = row0 + r * 32 + (lane & 31);
-          const int node = row < nrows ? row / 6 : 0;
-          const S* src = sp + (size_t)node * H + mt * 32 + g * 16;
+          const int node = row < nrows ? row / 6 : node0;
+          const S* src = sp_lds + (node - node0) * H + mt * 32 + g * 16;
           float v[16];
 #pragma unroll
           for (int vi = 0; vi < 16; ++vi) {
@@ -336,10 +430,13 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
 
     // J_D = G_1 W_1: one M-tile (14 used), K split over the waves
     {
+      if (blk + (int)gridDim.x < nblocks) sp_fetch(L - 1, (blk + gridDim.x) * R);
       f32x16 acc[1][C::RT];
-      int s0, s1;
-      C::split_k(wave, &s0, &s1);
-      C::template gemm<1>(acc, reinterpret_cast<const frag*>(net.rw[0]), C::KS_H, 0, s0, s1, lds, lane);
+      const int s0 = wave * C::SPLIT;
+      if (s0 < C::KS_H)
+        C::template gemm<1, C::SPLIT>(acc, reinterpret_cast<const frag*>(net.rw[0]), 1, C::KS_H, 0, s0, 0, lds, lane);
+      else
+        for (int r = 0; r < C::RT; ++r) acc[0][r] = f32x16{};
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < C::RT; ++r)
@@ -348,7 +445,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
           part[(wave * R + r * 32 + (lane & 31)) * 16 + (vi >> 2) * 8 + g * 4 + (vi & 3)] = acc[0][r][vi];
       __syncthreads();
       const float scale = P == P_FP8 ? net.wscale[0] * net.gscale[0] : 1.f;
-      for (int t = tid; t < R * kDin; t += NW * kWave) {
+      for (int t = tid; t < R * kDin; t += NT) {
         const int rr = t / kDin, c = t % kDin, row = row0 + rr;
         float s = 0.f;
         for (int w = 0; w < NW; ++w) s += part[(w * R + rr) * 16 + c];
@@ -359,9 +456,24 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
   }
 }
 
+// W_{L+1} (6 x H) reordered so that element j*H + stash_pos(k) holds W[j][k].
+__global__ void reorder_out_weights(const float* __restrict__ W, int H, float* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 6 * H; i += gridDim.x * blockDim.x) {
+    const int j = i / H, k = i % H;
+    out[j * H + stash_pos(k)] = W[i];
+  }
+}
+
+hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st) {
+  reorder_out_weights<<<(6 * H + 255) / 256, 256, 0, st>>>(W, H, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// Operand packing: fp32 matrix -> fragment-ordered compute-type copy.
-//   out[((mt*KS + s)*64 + lane)*E + j] = A[m][k],  m = 32 mt + lane % 32,
+// Operand packing: fp32 matrix -> fragment-ordered compute-type copy, K-step major
+// (all M-tiles of one K-step are contiguous, so the weights that lock-stepped
+// waves read at the same time are spread over the L2 channels):
+//   out[((s*MT + mt)*64 + lane)*E + j] = A[m][k],  m = 32 mt + lane % 32,
 //   k = slot_feature(s*E + j, lane / 32);  A = W (trans = 0) or W^T (trans = 1),
 //   W fp32 row-major [rows][cols].  Zero outside M x K.
 template <int P>
@@ -374,8 +486,8 @@ __global__ void pack_operand(const float* __restrict__ W, int cols, int M, int K
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
     const int j = idx % E;
     const int lane = (idx / E) % kWave;
-    const int s = (idx / ((long)E * kWave)) % KS;
-    const int mt = idx / ((long)E * kWave * KS);
+    const int mt = (idx / ((long)E * kWave)) % MT;
+    const int s = idx / ((long)E * kWave * MT);
     const int m = mt * 32 + (lane & 31);
     const int k = slot_feature(s * E + j, lane >> 5);
     float v = 0.f;

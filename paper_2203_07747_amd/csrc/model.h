@@ -26,6 +26,7 @@ struct Model {
   void* packed_rw[3][kMaxHidden] = {};
   // fp8 scales: weights [0, L], forward operands [L+1, 2L+1], reverse operands [2L+2, 3L+1]
   float* scales = nullptr;
+  float* w_out_s = nullptr;  // W_{L+1} with each row in stash order
   bool calibrated = false;
   // workspace (grown on demand)
   void* stash = nullptr;

@@ -11,6 +11,7 @@
 #include "../../include/rtn.h"
 #include "mlp_chain.h"
 #include "model.h"
+#include "profiler.h"
 
 using namespace rtn;
 
@@ -111,6 +112,7 @@ rtn_status rtn::Model::init(const rtn_mlp_desc& d) {
   if ((s = alloc((void**)&adam_m, n_params * 4))) return s;
   if ((s = alloc((void**)&adam_v, n_params * 4))) return s;
   if ((s = alloc((void**)&scales, (3 * L + 2) * 4))) return s;
+  if ((s = alloc((void**)&w_out_s, (size_t)kDout * H * 4))) return s;
   HIP_TRY(hipMemset(grad, 0, n_params * 4));
   HIP_TRY(hipMemset(adam_m, 0, n_params * 4));
   HIP_TRY(hipMemset(adam_v, 0, n_params * 4));
@@ -142,6 +144,7 @@ NetView rtn::Model::view(int prec) const {
     if (l < L) v.rw[l] = packed_rw[prec][l];
   }
   v.w_out = params + w_off[L];
+  v.w_out_s = w_out_s;
   v.wscale = scales;
   v.ascale = scales + (L + 1);
   v.gscale = scales + 2 * (L + 1);
@@ -156,6 +159,7 @@ rtn_status rtn::Model::repack(hipStream_t st) {
     HIP_TRY(launch_amax(params + w_off[l], (long)fo * fi, scales + l, st));
   }
   HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
+  HIP_TRY(launch_reorder_out(params + w_off[L], H, w_out_s, st));
   for (int p = 0; p < 3; ++p) {
     for (int l = 0; l <= L; ++l) {
       int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
@@ -350,14 +354,23 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
     float* y = f_D ? f_D : m->tmp;
     float* J = J_D ? J_D : m->tmp + (size_t)n_nodes * kDout;
     NetView v = m->view(prec);
-    HIP_TRY(launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, st));
-    HIP_TRY(launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, st));
+    {
+      ProfScope ps("mlp_forward_chain", st);
+      HIP_TRY(launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, st));
+    }
+    {
+      ProfScope ps("mlp_reverse_chain", st);
+      HIP_TRY(launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, st));
+    }
     fD_in = y;
     JD_in = J;
   } else {
     if (f_D) HIP_TRY(hipMemsetAsync(f_D, 0, (size_t)n_nodes * kDout * 4, st));
     if (J_D) HIP_TRY(hipMemsetAsync(J_D, 0, (size_t)n_nodes * kDout * kDin * 4, st));
   }
-  HIP_TRY(launch_rk4_linearize(n_nodes, qc, dt, x, u, fD_in, JD_in, x_next, A, B, status, st));
+  {
+    ProfScope ps("rk4_linearize", st);
+    HIP_TRY(launch_rk4_linearize(n_nodes, qc, dt, x, u, fD_in, JD_in, x_next, A, B, status, st));
+  }
   return RTN_OK;
 }

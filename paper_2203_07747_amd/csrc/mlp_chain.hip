@@ -58,8 +58,10 @@ template <int P, int H, int R, int NW> struct Chain {
   // reverse sweep: the activation derivatives of the nodes a row block touches
   static constexpr int SP_NODES = R % 6 == 0 ? R / 6 : R / 6 + 2;
   static constexpr int SP_ELEM = P == P_FP32 ? 4 : 2;
-  static constexpr int SP_BYTES = SP_NODES * H * SP_ELEM;
-  static constexpr int SP_CHUNKS_PER_THREAD = (SP_BYTES / 16 + NW * kWave - 1) / (NW * kWave);
+  static constexpr int SPS = H + 16 / SP_ELEM;  // LDS row stride (elements): 16-byte pad against bank conflicts
+  static constexpr int SP_BYTES = SP_NODES * SPS * SP_ELEM;
+  static constexpr int SP_ROW_CHUNKS = H * SP_ELEM / 16;
+  static constexpr int SP_CHUNKS_PER_THREAD = (SP_NODES * SP_ROW_CHUNKS + NW * kWave - 1) / (NW * kWave);
   static constexpr int REV_LDS_BYTES = LDS_BYTES + SP_BYTES;
   static_assert(MT % NW == 0, "width must split evenly over the waves");
   static_assert(MTW * RT * 16 <= (NW <= 4 ? 192 : 128), "accumulator budget");
@@ -197,6 +199,50 @@ __device__ inline void atomic_amax(float* p, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
 }
 
+// 16 consecutive stash values <-> floats, as 16-byte vector accesses.
+template <typename S> __device__ inline void store16(S* dst, const float (&v)[16]);
+template <> __device__ inline void store16<float>(float* dst, const float (&v)[16]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) reinterpret_cast<float4*>(dst)[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+}
+template <> __device__ inline void store16<uint16_t>(uint16_t* dst, const float (&v)[16]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    i32x4 w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      w[j] = (int)((uint32_t)f32_to_bf16_rne(v[8 * c + 2 * j]) | ((uint32_t)f32_to_bf16_rne(v[8 * c + 2 * j + 1]) << 16));
+    reinterpret_cast<i32x4*>(dst)[c] = w;
+  }
+}
+// RL consecutive stash values (RL = 1, 8 or 16) -> floats
+template <int RL> __device__ inline void load_run(const float* src, float* v) {
+  if constexpr (RL == 1) {
+    v[0] = src[0];
+  } else {
+#pragma unroll
+    for (int c = 0; c < RL / 4; ++c) {
+      const float4 t = reinterpret_cast<const float4*>(src)[c];
+      v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+    }
+  }
+}
+template <int RL> __device__ inline void load_run(const uint16_t* src, float* v) {
+  if constexpr (RL == 1) {
+    v[0] = __uint_as_float(((uint32_t)src[0]) << 16);
+  } else {
+#pragma unroll
+    for (int c = 0; c < RL / 8; ++c) {
+      const i32x4 t = reinterpret_cast<const i32x4*>(src)[c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[8 * c + 2 * j] = __uint_as_float(((uint32_t)t[j]) << 16);
+        v[8 * c + 2 * j + 1] = __uint_as_float(((uint32_t)t[j]) & 0xffff0000u);
+      }
+    }
+  }
+}
+
 template <typename S> __device__ inline S to_stash(float v);
 template <> __device__ inline float to_stash<float>(float v) { return v; }
 template <> __device__ inline uint16_t to_stash<uint16_t>(float v) { return f32_to_bf16_rne(v); }
@@ -240,7 +286,12 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
           else z = u[(size_t)row * kNu + (k - 10)];                  // u
         }
         v[j] = z;
-        if (amax && row < n && k < kDin) atomic_amax(&amax[0], z);
+      }
+      if (amax) {  // calibration only: max |z_0| (padding slots hold zeros)
+        float m = 0.f;
+#pragma unroll
+        for (int j = 0; j < C::E; ++j) m = fmaxf(m, fabsf(v[j]));
+        atomic_amax(&amax[0], m);
       }
       C::put_slots(lds, rt, s, l, C::KS_1, v, P == P_FP8 ? 1.f / net.ascale[0] : 1.f);
     }
@@ -260,17 +311,20 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
       const float inv_next = P == P_FP8 ? 1.f / net.ascale[layer + 1] : 1.f;
       const float* bias = net.bias[layer];
       S* st = stash + (size_t)layer * n * H;
+      float lmax = 0.f;  // calibration: this lane's max |h|
 #pragma unroll
       for (int i = 0; i < C::MTW; ++i) {
         const int mt = wave * C::MTW + i;
+        float bm[16];
+#pragma unroll
+        for (int vi = 0; vi < 16; ++vi) bm[vi] = bias[mt * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3)];
 #pragma unroll
         for (int r = 0; r < C::RT; ++r) {
           const int row = row0 + r * 32 + (lane & 31);
           float h[16], sp[16];
 #pragma unroll
           for (int vi = 0; vi < 16; ++vi) {
-            const int m = mt * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3);
-            const float a = acc[i][r][vi] * scale + bias[m];
+            const float a = acc[i][r][vi] * scale + bm[vi];
             if (net.act == 0) {
               const float sg = 1.f / (1.f + __expf(-a));
               h[vi] = a * sg;
@@ -279,16 +333,16 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
               h[vi] = a;
               sp[vi] = 1.f;
             }
-            if (amax && row < n) atomic_amax(&amax[layer + 1], h[vi]);
           }
-          if (row < n) {
-            S* dst = st + (size_t)row * H + mt * 32 + g * 16;
+          if (amax && row < n) {
 #pragma unroll
-            for (int vi = 0; vi < 16; ++vi) dst[vi] = to_stash<S>(sp[vi]);
+            for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(h[vi]));
           }
+          if (row < n) store16<S>(st + (size_t)row * H + mt * 32 + g * 16, sp);
           C::put_operand(lds, r, mt, lane, h, inv_next);
         }
       }
+      if (amax) atomic_amax(&amax[layer + 1], lmax);
       __syncthreads();
     }
 
@@ -366,7 +420,8 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int idx = tid + c * NT;
-      if (idx < C::SP_BYTES / 16) sp_lds4[idx] = sp_reg[c];
+      const int nd = idx / C::SP_ROW_CHUNKS, w = idx - nd * C::SP_ROW_CHUNKS;
+      if (nd < C::SP_NODES) sp_lds4[nd * (C::SPS * C::SP_ELEM / 16) + w] = sp_reg[c];
     }
   };
 
@@ -376,26 +431,35 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     const int node0 = row0 / 6;
     sp_park();
     __syncthreads();
-    // G_L[row][k] = W_{L+1}[row % 6][k] * act'(a_L)[row / 6][k]
+    // G_L[row][k] = W_{L+1}[row % 6][k] * act'(a_L)[row / 6][k]; the E slots of one
+    // (row tile, K-step, lane) item are runs of consecutive stash positions
     {
       const float inv = P == P_FP8 ? 1.f / net.gscale[L - 1] : 1.f;
+      constexpr int RL = C::E < 16 ? C::E : 16;
+      float lmax = 0.f;
       for (int it = tid; it < C::RT * C::KS_H * kWave; it += NT) {
         const int l = it % kWave, s = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
         const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
         const bool live = row < nrows;
         const int node = live ? row / 6 : node0, j6 = live ? row - 6 * node : 0;
-        const S* spn = sp_lds + (node - node0) * H;
-        const float* wo = net.w_out_s + j6 * H;
         float v[C::E];
 #pragma unroll
-        for (int j = 0; j < C::E; ++j) {
-          const int q = s * C::E + j;
-          const int pos = 32 * (q >> 4) + gg * 16 + (q & 15);  // stash order of slot q
-          v[j] = live ? wo[pos] * from_stash(spn[pos]) : 0.f;
-          if (amax && live) atomic_amax(&amax[L - 1], v[j]);
+        for (int run = 0; run < C::E / RL; ++run) {
+          const int q0 = s * C::E + run * RL;
+          const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
+          float spv[RL], wv[RL];
+          load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, spv);
+          load_run<RL>(net.w_out_s + j6 * H + pos, wv);
+#pragma unroll
+          for (int t = 0; t < RL; ++t) v[run * RL + t] = live ? wv[t] * spv[t] : 0.f;
+        }
+        if (amax) {
+#pragma unroll
+          for (int j = 0; j < C::E; ++j) lmax = fmaxf(lmax, fabsf(v[j]));
         }
         C::put_slots(lds, rt, s, l, C::KS_H, v, inv);
       }
+      if (amax) atomic_amax(&amax[L - 1], lmax);
     }
     __syncthreads();
 
@@ -408,6 +472,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
       __syncthreads();
       const float scale = P == P_FP8 ? net.wscale[layer] * net.gscale[layer] : 1.f;
       const float inv_next = P == P_FP8 ? 1.f / net.gscale[layer - 1] : 1.f;
+      float lmax = 0.f;
 #pragma unroll
       for (int i = 0; i < C::MTW; ++i) {
         const int mt = wave * C::MTW + i;
@@ -415,16 +480,19 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
         for (int r = 0; r < C::RT; ++r) {
           const int row = row0 + r * 32 + (lane & 31);
           const int node = row < nrows ? row / 6 : node0;
-          const S* src = sp_lds + (node - node0) * H + mt * 32 + g * 16;
+          float spv[16];
+          load_run<16>(sp_lds + (node - node0) * C::SPS + mt * 32 + g * 16, spv);
           float v[16];
 #pragma unroll
-          for (int vi = 0; vi < 16; ++vi) {
-            v[vi] = acc[i][r][vi] * scale * from_stash(src[vi]);
-            if (amax && row < nrows) atomic_amax(&amax[layer - 1], v[vi]);
+          for (int vi = 0; vi < 16; ++vi) v[vi] = acc[i][r][vi] * scale * spv[vi];
+          if (amax && row < nrows) {
+#pragma unroll
+            for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(v[vi]));
           }
           C::put_operand(lds, r, mt, lane, v, inv_next);
         }
       }
+      if (amax) atomic_amax(&amax[layer - 1], lmax);
       __syncthreads();
     }
 

@@ -34,11 +34,11 @@ namespace rtn {
 // registers: <= 128 with two waves per SIMD (8 waves), <= 192 with one wave per
 // SIMD (4 waves), where the accumulators live in AGPRs.
 template <int P, int H> struct ChainShape {
-  static constexpr bool ONE_PER_SIMD = P != P_FP32 && H == 512;
+  static constexpr bool ONE_PER_SIMD = P == P_BF16 && H == 512;
   static constexpr int NW = ONE_PER_SIMD ? 4 : (H >= 256 ? 8 : H / 32);
   static constexpr int R = P == P_FP32 ? (H <= 256 ? 128 : (H == 512 ? 64 : 32))
                          : P == P_BF16 ? (H <= 256 ? 128 : (H == 512 ? 96 : 64))
-                                       : (H <= 256 ? 128 : (H == 512 ? 96 : 64));
+                                       : (H <= 256 ? 128 : 64);
 };
 
 template <int P, int H, int R, int NW> struct Chain {
@@ -62,7 +62,11 @@ template <int P, int H, int R, int NW> struct Chain {
   static constexpr int SP_BYTES = SP_NODES * SPS * SP_ELEM;
   static constexpr int SP_ROW_CHUNKS = H * SP_ELEM / 16;
   static constexpr int SP_CHUNKS_PER_THREAD = (SP_NODES * SP_ROW_CHUNKS + NW * kWave - 1) / (NW * kWave);
-  static constexpr int REV_LDS_BYTES = LDS_BYTES + SP_BYTES;
+  // output weights stay resident in LDS for the whole kernel when they fit
+  static constexpr int WOS = H + 4;  // LDS row stride (floats): 16-byte pad against bank conflicts
+  static constexpr bool WO_IN_LDS = LDS_BYTES + SP_BYTES + kDout * WOS * 4 <= 160 * 1024;
+  static constexpr int WO_BYTES = WO_IN_LDS ? kDout * WOS * 4 : 0;
+  static constexpr int REV_LDS_BYTES = LDS_BYTES + SP_BYTES + WO_BYTES;
   static_assert(MT % NW == 0, "width must split evenly over the waves");
   static_assert(MTW * RT * 16 <= (NW <= 4 ? 192 : 128), "accumulator budget");
 
@@ -76,9 +80,23 @@ template <int P, int H, int R, int NW> struct Chain {
   // acc[i][r] = sum over NSTEPS K-steps from s0 of A(mt0+i, s) * B(r, s), NMT M-tiles.
   // Weight fragments stream through a PD-deep register ring (loads are issued PD steps
   // ahead of their use, hiding L2 latency); LDS operand fragments are double-buffered.
+  // B operand read from the LDS operand region
+  struct LdsB {
+    static constexpr bool kPrefetch = true;  // read the next step's fragments one step ahead
+    const elem* lds;
+    int KS;
+    __device__ inline frag operator()(int r, int s, int lane) const { return lds_frag(lds, r, s, lane, KS); }
+  };
+
   template <int NMT, int NSTEPS>
   __device__ static inline void gemm(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int MTALL, int KS,
                                      int mt0, int s0, int rot, const elem* lds, int lane) {
+    gemm_src<NMT, NSTEPS>(acc, Wp, MTALL, mt0, s0, rot, LdsB{lds, KS}, lane);
+  }
+
+  template <int NMT, int NSTEPS, class BSrc>
+  __device__ static inline void gemm_src(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int MTALL,
+                                         int mt0, int s0, int rot, const BSrc& bsrc, int lane) {
     // ring depth: up to 4 steps, at most 128 (two waves per SIMD) or 256 (one wave
     // per SIMD) bytes of weight fragments per lane
     constexpr int PD0 = (NW <= 4 ? 256 : 128) / (NMT * (int)sizeof(frag));
@@ -101,23 +119,30 @@ template <int P, int H, int R, int NW> struct Chain {
       for (int i = 0; i < NMT; ++i) a[d][i] = wfrag(d, i);
     frag b[RT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) b[r] = lds_frag(lds, r, kstep(0), lane, KS);
+    for (int r = 0; r < RT; ++r) b[r] = bsrc(r, kstep(0), lane);
     // steady state: every step prefetches the weights PD steps ahead
     for (int g = 0; g < NSTEPS - PD; g += PD) {
 #pragma unroll
       for (int d = 0; d < PD; ++d) {
         const int s = g + d;
         frag bn[RT];
+        if constexpr (BSrc::kPrefetch) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) bn[r] = lds_frag(lds, r, kstep(s + 1), lane, KS);
+          for (int r = 0; r < RT; ++r) bn[r] = bsrc(r, kstep(s + 1), lane);
+        } else if (s > 0) {
+#pragma unroll
+          for (int r = 0; r < RT; ++r) b[r] = bsrc(r, kstep(s), lane);
+        }
 #pragma unroll
         for (int i = 0; i < NMT; ++i)
 #pragma unroll
           for (int r = 0; r < RT; ++r) acc[i][r] = M::mma(a[d][i], b[r], acc[i][r]);
 #pragma unroll
         for (int i = 0; i < NMT; ++i) a[d][i] = wfrag(s + PD, i);
+        if constexpr (BSrc::kPrefetch) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) b[r] = bn[r];
+          for (int r = 0; r < RT; ++r) b[r] = bn[r];
+        }
         // keep each step's loads where they are issued: PD steps ahead of their use
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -127,17 +152,24 @@ template <int P, int H, int R, int NW> struct Chain {
     for (int d = 0; d < PD; ++d) {
       const int s = NSTEPS - PD + d;
       frag bn[RT];
-      if (d + 1 < PD) {
+      if constexpr (BSrc::kPrefetch) {
+        if (d + 1 < PD) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) bn[r] = lds_frag(lds, r, kstep(s + 1), lane, KS);
+          for (int r = 0; r < RT; ++r) bn[r] = bsrc(r, kstep(s + 1), lane);
+        }
+      } else if (s > 0) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) b[r] = bsrc(r, kstep(s), lane);
       }
 #pragma unroll
       for (int i = 0; i < NMT; ++i)
 #pragma unroll
         for (int r = 0; r < RT; ++r) acc[i][r] = M::mma(a[d][i], b[r], acc[i][r]);
-      if (d + 1 < PD) {
+      if constexpr (BSrc::kPrefetch) {
+        if (d + 1 < PD) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) b[r] = bn[r];
+          for (int r = 0; r < RT; ++r) b[r] = bn[r];
+        }
       }
     }
   }
@@ -157,7 +189,7 @@ template <int P, int H, int R, int NW> struct Chain {
         i32x4 w;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          w[j] = (int)((uint32_t)f32_to_bf16_rne(v[8 * h + 2 * j]) | ((uint32_t)f32_to_bf16_rne(v[8 * h + 2 * j + 1]) << 16));
+          w[j] = (int)pack_bf16x2(v[8 * h + 2 * j], v[8 * h + 2 * j + 1]);
         *reinterpret_cast<i32x4*>(lds + lidx(rt, 2 * mt + h, lane, KS_H)) = w;
       }
     } else {
@@ -170,6 +202,25 @@ template <int P, int H, int R, int NW> struct Chain {
     }
   }
 
+  // E float slot values -> one operand fragment
+  __device__ static inline frag to_frag(const float* v, float inv_scale) {
+    if constexpr (P == P_FP32) {
+      return v[0];
+    } else if constexpr (P == P_BF16) {
+      i32x4 w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = (int)pack_bf16x2(v[2 * j], v[2 * j + 1]);
+      return __builtin_bit_cast(frag, w);
+    } else {
+      i32x8 w;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        w[j] = (int)(f32x2_to_e4m3(v[4 * j] * inv_scale, v[4 * j + 1] * inv_scale) |
+                     (f32x2_to_e4m3(v[4 * j + 2] * inv_scale, v[4 * j + 3] * inv_scale) << 16));
+      return w;
+    }
+  }
+
   // Write one operand element block (E slots of lane `lane`, K-step s) from float values.
   __device__ static inline void put_slots(elem* lds, int rt, int s, int lane, int KS, const float* v, float inv_scale) {
     elem* dst = lds + lidx(rt, s, lane, KS);
@@ -178,7 +229,7 @@ template <int P, int H, int R, int NW> struct Chain {
     } else if constexpr (P == P_BF16) {
       i32x4 w;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) w[j] = (int)((uint32_t)f32_to_bf16_rne(v[2 * j]) | ((uint32_t)f32_to_bf16_rne(v[2 * j + 1]) << 16));
+      for (int j = 0; j < 4; ++j) w[j] = (int)pack_bf16x2(v[2 * j], v[2 * j + 1]);
       *reinterpret_cast<i32x4*>(dst) = w;
     } else {
 #pragma unroll
@@ -211,7 +262,7 @@ template <> __device__ inline void store16<uint16_t>(uint16_t* dst, const float 
     i32x4 w;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      w[j] = (int)((uint32_t)f32_to_bf16_rne(v[8 * c + 2 * j]) | ((uint32_t)f32_to_bf16_rne(v[8 * c + 2 * j + 1]) << 16));
+      w[j] = (int)pack_bf16x2(v[8 * c + 2 * j], v[8 * c + 2 * j + 1]);
     reinterpret_cast<i32x4*>(dst)[c] = w;
   }
 }
@@ -396,6 +447,9 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
   float* part = reinterpret_cast<float*>(smem);
   S* sp_lds = reinterpret_cast<S*>(smem + C::LDS_BYTES);
   i32x4* sp_lds4 = reinterpret_cast<i32x4*>(smem + C::LDS_BYTES);
+  float* wo_lds = reinterpret_cast<float*>(smem + C::LDS_BYTES + C::SP_BYTES);
+  const float* wo = C::WO_IN_LDS ? wo_lds : net.w_out_s;
+  const int wo_stride = C::WO_IN_LDS ? C::WOS : H;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
   const int nrows = 6 * n;
@@ -425,6 +479,12 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     }
   };
 
+  if constexpr (C::WO_IN_LDS) {
+    for (int i = tid; i < kDout * H / 4; i += NT) {
+      const int j = i / (H / 4), c = i - j * (H / 4);
+      reinterpret_cast<float4*>(wo_lds + j * C::WOS)[c] = reinterpret_cast<const float4*>(net.w_out_s)[i];
+    }
+  }
   if (blockIdx.x < nblocks) sp_fetch(L - 1, blockIdx.x * R);
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int row0 = blk * R;
@@ -433,10 +493,11 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     __syncthreads();
     // G_L[row][k] = W_{L+1}[row % 6][k] * act'(a_L)[row / 6][k]; the E slots of one
     // (row tile, K-step, lane) item are runs of consecutive stash positions
+    constexpr int RL = C::E < 16 ? C::E : 16;
     {
       const float inv = P == P_FP8 ? 1.f / net.gscale[L - 1] : 1.f;
-      constexpr int RL = C::E < 16 ? C::E : 16;
       float lmax = 0.f;
+#pragma unroll 4
       for (int it = tid; it < C::RT * C::KS_H * kWave; it += NT) {
         const int l = it % kWave, s = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
         const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
@@ -449,7 +510,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
           const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
           float spv[RL], wv[RL];
           load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, spv);
-          load_run<RL>(net.w_out_s + j6 * H + pos, wv);
+          load_run<RL>(wo + j6 * wo_stride + pos, wv);
 #pragma unroll
           for (int t = 0; t < RL; ++t) v[run * RL + t] = live ? wv[t] * spv[t] : 0.f;
         }
@@ -464,27 +525,47 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     __syncthreads();
 
     for (int layer = L - 1; layer >= 1; --layer) {  // weights W_{layer+1}^T, stash of h_layer
-      sp_fetch(layer - 1, row0);
       f32x16 acc[C::MTW][C::RT];
-      C::template gemm<C::MTW, C::KS_H>(acc, reinterpret_cast<const frag*>(net.rw[layer]), C::MT, C::KS_H, wave * C::MTW,
-                                        0, blk, lds, lane);
+      sp_fetch(layer - 1, row0);
+      C::template gemm<C::MTW, C::KS_H>(acc, reinterpret_cast<const frag*>(net.rw[layer]), C::MT, C::KS_H,
+                                        wave * C::MTW, 0, blk, lds, lane);
       sp_park();
       __syncthreads();
       const float scale = P == P_FP8 ? net.wscale[layer] * net.gscale[layer] : 1.f;
       const float inv_next = P == P_FP8 ? 1.f / net.gscale[layer - 1] : 1.f;
       float lmax = 0.f;
+      // with one wave per SIMD there are registers to read all of this wave's
+      // activation-derivative runs (16 stash values = 32 or 64 bytes each, kept
+      // packed) before their first use
+      constexpr bool PRE = NW <= 4;
+      constexpr int PI = PRE ? C::MTW : 1, PR = PRE ? C::RT : 1;
+      constexpr int RUN_CH = 16 * (int)sizeof(S) / 16;  // 16-byte chunks per run
+      i32x4 spraw[PI][PR][RUN_CH];
+      auto raw_load = [&](int i, int r, int mt, int row) {
+        const int node = row < nrows ? row / 6 : node0;
+        const i32x4* src = reinterpret_cast<const i32x4*>(sp_lds + (node - node0) * C::SPS + mt * 32 + g * 16);
+#pragma unroll
+        for (int c = 0; c < RUN_CH; ++c) spraw[i][r][c] = src[c];
+      };
+      if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < C::MTW; ++i)
+#pragma unroll
+          for (int r = 0; r < C::RT; ++r) raw_load(i, r, wave * C::MTW + i, row0 + r * 32 + (lane & 31));
+      }
 #pragma unroll
       for (int i = 0; i < C::MTW; ++i) {
         const int mt = wave * C::MTW + i;
 #pragma unroll
         for (int r = 0; r < C::RT; ++r) {
           const int row = row0 + r * 32 + (lane & 31);
-          const int node = row < nrows ? row / 6 : node0;
-          float spv[16];
-          load_run<16>(sp_lds + (node - node0) * C::SPS + mt * 32 + g * 16, spv);
+          const int pi = PRE ? i : 0, pr = PRE ? r : 0;
+          if constexpr (!PRE) raw_load(0, 0, mt, row);
+          float sv[16];
+          load_run<16>(reinterpret_cast<const S*>(spraw[pi][pr]), sv);
           float v[16];
 #pragma unroll
-          for (int vi = 0; vi < 16; ++vi) v[vi] = acc[i][r][vi] * scale * spv[vi];
+          for (int vi = 0; vi < 16; ++vi) v[vi] = acc[i][r][vi] * scale * sv[vi];
           if (amax && row < nrows) {
 #pragma unroll
             for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(v[vi]));

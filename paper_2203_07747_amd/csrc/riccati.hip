@@ -1,0 +1,179 @@
+// Feedback phase: batched backward Riccati recursion in fp64 (Sec. IV-B; QP of
+// Sec. IV-A with the continuity condition eq. (2) and the quadratic cost of
+// Sec. VI).  For each instance, from P_N = Q_N, p_N = q_N and k = N-1 down to 0:
+//
+//   Qxx = Q + A^T P A,  Quu = R + B^T P B,  Qux = B^T P A,   g = P c + p
+//   qx  = q + A^T g,    qu  = r + B^T g
+//   K   = -Quu^{-1} Qux,  kff = -Quu^{-1} qu               (Cholesky of the 4x4 Quu)
+//   P  <- sym(Qxx + Qux^T K),  p <- qx + Qux^T kff
+//
+// One 64-lane workgroup per instance; the 13x13 matrices live in LDS in fp64
+// and each lane owns a few of their entries.  The recursion is sequential in k,
+// so instances (not nodes) are the parallel axis.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "mlp_chain.h"
+
+namespace rtn {
+
+constexpr int NX = 13, NU = 4;
+
+struct RiccatiArgs {
+  const int* offsets;   // [n_inst + 1]
+  const double* Q;      // 13x13
+  const double* R;      // 4x4
+  const double* QN;     // 13x13
+  const float* A;       // [n][13][13]
+  const float* B;       // [n][13][4]
+  const double* c;      // nullable [n][13]
+  const double* q;      // nullable [n][13]
+  const double* r;      // nullable [n][4]
+  const double* qN;     // nullable [n_inst][13]
+  double* K;            // [n][4][13]
+  double* kff;          // [n][4]
+  double* P;            // nullable [n][13][13]
+};
+
+__global__ void __launch_bounds__(64) riccati_kernel(RiccatiArgs a) {
+  __shared__ double sQ[NX * NX], sR[NU * NU];
+  __shared__ double sA[NX * NX], sB[NX * NU], sP[NX * NX], sPA[NX * NX], sPB[NX * NU];
+  __shared__ double sQxx[NX * NX], sQux[NU * NX], sQuu[NU * NU], sK[NU * NX];
+  __shared__ double sc[NX], sp[NX], sg[NX], sqx[NX], squ[NU], skff[NU], sq[NX], sr[NU];
+  const int inst = blockIdx.x, t = threadIdx.x;
+  const int k0 = a.offsets[inst], k1 = a.offsets[inst + 1];
+  for (int i = t; i < NX * NX; i += 64) {
+    sQ[i] = a.Q[i];
+    sP[i] = a.QN[i];
+  }
+  for (int i = t; i < NU * NU; i += 64) sR[i] = a.R[i];
+  for (int i = t; i < NX; i += 64) sp[i] = a.qN ? a.qN[(size_t)inst * NX + i] : 0.0;
+  __syncthreads();
+  for (int k = k1 - 1; k >= k0; --k) {
+    // stage the node's data (fp32 A, B promoted exactly)
+    for (int i = t; i < NX * NX; i += 64) sA[i] = (double)a.A[(size_t)k * NX * NX + i];
+    if (t < NX * NU) sB[t] = (double)a.B[(size_t)k * NX * NU + t];
+    if (t < NX) {
+      sc[t] = a.c ? a.c[(size_t)k * NX + t] : 0.0;
+      sq[t] = a.q ? a.q[(size_t)k * NX + t] : 0.0;
+    }
+    if (t < NU) sr[t] = a.r ? a.r[(size_t)k * NU + t] : 0.0;
+    __syncthreads();
+    // P A, P B, g = P c + p
+    for (int e = t; e < NX * NX; e += 64) {
+      const int i = e / NX, j = e % NX;
+      double s = 0.0;
+      for (int m = 0; m < NX; ++m) s += sP[i * NX + m] * sA[m * NX + j];
+      sPA[e] = s;
+    }
+    if (t < NX * NU) {
+      const int i = t / NU, j = t % NU;
+      double s = 0.0;
+      for (int m = 0; m < NX; ++m) s += sP[i * NX + m] * sB[m * NU + j];
+      sPB[t] = s;
+    }
+    if (t < NX) {
+      double s = sp[t];
+      for (int m = 0; m < NX; ++m) s += sP[t * NX + m] * sc[m];
+      sg[t] = s;
+    }
+    __syncthreads();
+    // Qxx, Qux, Quu, qx, qu
+    for (int e = t; e < NX * NX; e += 64) {
+      const int i = e / NX, j = e % NX;
+      double s = sQ[e];
+      for (int m = 0; m < NX; ++m) s += sA[m * NX + i] * sPA[m * NX + j];
+      sQxx[e] = s;
+    }
+    if (t < NU * NX) {
+      const int u = t / NX, j = t % NX;
+      double s = 0.0;
+      for (int m = 0; m < NX; ++m) s += sB[m * NU + u] * sPA[m * NX + j];
+      sQux[t] = s;
+    }
+    if (t < NU * NU) {
+      const int u = t / NU, v = t % NU;
+      double s = sR[t];
+      for (int m = 0; m < NX; ++m) s += sB[m * NU + u] * sPB[m * NU + v];
+      sQuu[t] = s;
+    }
+    if (t < NX) {
+      double s = sq[t];
+      for (int m = 0; m < NX; ++m) s += sA[m * NX + t] * sg[m];
+      sqx[t] = s;
+    }
+    if (t < NU) {
+      double s = sr[t];
+      for (int m = 0; m < NX; ++m) s += sB[m * NU + t] * sg[m];
+      squ[t] = s;
+    }
+    __syncthreads();
+    // K = -Quu^-1 Qux (columns 0..12), kff = -Quu^-1 qu (column 13): each lane
+    // factors Quu = L L^T itself and solves its own right-hand side.
+    if (t <= NX) {
+      double Lc[NU][NU] = {};
+      bool ok = true;
+      for (int j = 0; j < NU; ++j) {
+        double d = sQuu[j * NU + j];
+        for (int m = 0; m < j; ++m) d -= Lc[j][m] * Lc[j][m];
+        ok = ok && d > 0.0;
+        const double ljj = sqrt(d);
+        Lc[j][j] = ljj;
+        for (int i = j + 1; i < NU; ++i) {
+          double s = 0.5 * (sQuu[i * NU + j] + sQuu[j * NU + i]);
+          for (int m = 0; m < j; ++m) s -= Lc[i][m] * Lc[j][m];
+          Lc[i][j] = s / ljj;
+        }
+      }
+      double y[NU], x[NU];
+      for (int i = 0; i < NU; ++i) {
+        double s = t < NX ? sQux[i * NX + t] : squ[i];
+        for (int m = 0; m < i; ++m) s -= Lc[i][m] * y[m];
+        y[i] = s / Lc[i][i];
+      }
+      for (int i = NU - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int m = i + 1; m < NU; ++m) s -= Lc[m][i] * x[m];
+        x[i] = s / Lc[i][i];
+      }
+      const double nan = __builtin_nan("");
+      for (int i = 0; i < NU; ++i) {
+        const double v = ok ? -x[i] : nan;
+        if (t < NX) sK[i * NX + t] = v;
+        else skff[i] = v;
+      }
+    }
+    __syncthreads();
+    // outputs of node k and the value function before it
+    for (int e = t; e < NU * NX; e += 64) a.K[(size_t)k * NU * NX + e] = sK[e];
+    if (t < NU) a.kff[(size_t)k * NU + t] = skff[t];
+    for (int e = t; e < NX * NX; e += 64) {
+      const int i = e / NX, j = e % NX;
+      double pij = sQxx[e], pji = sQxx[j * NX + i];
+      for (int u = 0; u < NU; ++u) {
+        pij += sQux[u * NX + i] * sK[u * NX + j];
+        pji += sQux[u * NX + j] * sK[u * NX + i];
+      }
+      const double v = 0.5 * (pij + pji);
+      sP[e] = v;
+      if (a.P) a.P[(size_t)k * NX * NX + e] = v;
+    }
+    if (t < NX) {
+      double s = sqx[t];
+      for (int u = 0; u < NU; ++u) s += sQux[u * NX + t] * skff[u];
+      sp[t] = s;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const double* R, const double* QN,
+                          const float* A, const float* B, const double* c, const double* q, const double* r,
+                          const double* qN, double* K, double* kff, double* P, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  RiccatiArgs a{offsets, Q, R, QN, A, B, c, q, r, qN, K, kff, P};
+  riccati_kernel<<<n_inst, 64, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace rtn

@@ -374,3 +374,48 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
   }
   return RTN_OK;
 }
+
+extern "C" rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes, const float* A,
+                                  const float* B, const double* c, const double* Q_host, const double* R_host,
+                                  const double* QN_host, const double* q, const double* r, const double* qN,
+                                  double* K, double* kff, double* P, void* stream) {
+  rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
+  if (s) return s;
+  if (!Q_host || !R_host || !QN_host) return fail(RTN_EINVAL, "Q_host, R_host and QN_host are required");
+  for (int i = 0; i < 13 * 13; ++i)
+    if (!std::isfinite(Q_host[i]) || !std::isfinite(QN_host[i])) return fail(RTN_EINVAL, "Q or Q_N is not finite");
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(R_host[i])) return fail(RTN_EINVAL, "R is not finite");
+  if (n_nodes == 0) return RTN_OK;
+  if (!A || !B) return fail(RTN_EINVAL, "A and B must be device pointers");
+  if (!K || !kff) return fail(RTN_EINVAL, "K and kff must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  // constants and instance ranges travel in one stream-ordered scratch block
+  const size_t nd = 13 * 13 + 16 + 13 * 13;
+  std::vector<char> host(nd * 8 + (size_t)(n_inst + 1) * 4);
+  memcpy(host.data(), Q_host, 169 * 8);
+  memcpy(host.data() + 169 * 8, R_host, 16 * 8);
+  memcpy(host.data() + 185 * 8, QN_host, 169 * 8);
+  int32_t* off = reinterpret_cast<int32_t*>(host.data() + nd * 8);
+  if (offsets_host) {
+    memcpy(off, offsets_host, (size_t)(n_inst + 1) * 4);
+  } else {
+    off[0] = 0;
+    off[1] = n_nodes;
+  }
+  void* dev = nullptr;
+  hipError_t e = hipMallocAsync(&dev, host.size(), st);
+  if (e != hipSuccess) return fail(RTN_ENOMEM, "hipMallocAsync(%zu bytes): %s", host.size(), hipGetErrorString(e));
+  e = hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    const double* d = reinterpret_cast<const double*>(dev);
+    ProfScope ps("riccati", st);
+    e = launch_riccati(n_inst, reinterpret_cast<const int*>((char*)dev + nd * 8), d, d + 169, d + 185, A, B, c, q, r,
+                       qN, K, kff, P, st);
+  }
+  // the pageable source is copied before hipMemcpyAsync returns; free when the kernel is done
+  hipError_t e2 = hipFreeAsync(dev, st);
+  if (e != hipSuccess) return hip_fail(e, "rtn_riccati");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return RTN_OK;
+}

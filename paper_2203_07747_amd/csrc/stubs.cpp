@@ -6,11 +6,6 @@
 
 extern "C" {
 
-rtn_status rtn_riccati(int32_t, const int32_t*, int32_t, const float*, const float*, const double*, const double*,
-                       const double*, const double*, const double*, const double*, const double*, double*, double*,
-                       double*, void*) {
-  return RTN_ENOTSUP;
-}
 rtn_status rtn_mlp_forward(rtn_model*, int32_t, int32_t, const float*, float*, void*) { return RTN_ENOTSUP; }
 rtn_status rtn_mlp_backward(rtn_model*, int32_t, const float*, float*, void*) { return RTN_ENOTSUP; }
 rtn_status rtn_model_zero_grad(rtn_model*, void*) { return RTN_ENOTSUP; }

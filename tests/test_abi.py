@@ -96,3 +96,18 @@ def test_model_calls_reject_null(lib):
     assert lib.rtn_model_destroy(None) == RTN_OK
     assert lib.rtn_model_set_params(None, None) == RTN_EINVAL
     assert lib.rtn_model_calibrate(None, 4, None, None, None) == RTN_EINVAL
+
+
+def test_riccati_validation(lib):
+    Q = np.eye(13); R = 0.1 * np.eye(4)
+    qp = Q.ctypes.data_as(ctypes.c_void_p); rp = R.ctypes.data_as(ctypes.c_void_p)
+    z = ctypes.c_void_p(16)
+    assert lib.rtn_riccati(1, None, 0, None, None, None, qp, rp, qp, None, None, None, None, None, None, None) == RTN_OK
+    assert lib.rtn_riccati(1, None, 3, None, None, None, None, rp, qp, None, None, None, z, z, None, None) == RTN_EINVAL
+    assert lib.rtn_riccati(1, None, 3, None, None, None, qp, rp, qp, None, None, None, z, z, None, None) == RTN_EINVAL
+    off = np.array([0, 2, 2], dtype=np.int32)
+    assert lib.rtn_riccati(2, off.ctypes.data_as(ctypes.c_void_p), 2, z, z, None, qp, rp, qp, None, None, None, z, z,
+                           None, None) == RTN_EINVAL
+    Rbad = R.copy(); Rbad[0, 0] = np.inf
+    assert lib.rtn_riccati(1, None, 3, z, z, None, qp, Rbad.ctypes.data_as(ctypes.c_void_p), qp, None, None, None,
+                           z, z, None, None) == RTN_EINVAL

@@ -1,0 +1,102 @@
+"""GPU parity of rtn_riccati (fp64) against the oracle's recursion and brute-force KKT."""
+import numpy as np
+import pytest
+
+from workload import config_workload, sample_horizons, offsets_from_horizons
+from oracle.riccati import riccati_batched, kkt_bruteforce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def random_lq(n, seed):
+    rng = np.random.default_rng(seed)
+    A = (np.eye(13) + 0.1 * rng.normal(size=(n, 13, 13))).astype(np.float32)
+    B = (0.2 * rng.normal(size=(n, 13, 4))).astype(np.float32)
+    return A, B, rng
+
+
+def gpu_riccati(torch, A, B, Q, R, QN, off, c=None, q=None, r=None, qN=None):
+    import paper_2203_07747_amd as rtn
+    print(f"[gpu] riccati n={A.shape[0]} n_inst={len(off) - 1}", flush=True)
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = rtn.riccati(dev(A), dev(B), Q, R, QN, offsets=off, c=dev(c), q=dev(q), r=dev(r), qN=dev(qN), want_P=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def rel_max(a, b):
+    a = a.reshape(a.shape[0], -1); b = b.reshape(b.shape[0], -1)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)))
+
+
+def test_ragged_instances_with_affine_terms(torch):
+    hz = sample_horizons(37, 1, 12, seed=4)
+    off = offsets_from_horizons(hz)
+    n = int(off[-1])
+    A, B, rng = random_lq(n, 1)
+    c = rng.normal(size=(n, 13)) * 0.1
+    q = rng.normal(size=(n, 13)); r = rng.normal(size=(n, 4)); qN = rng.normal(size=(len(hz), 13))
+    Q = np.eye(13); R = 0.1 * np.eye(4); QN = 2.0 * np.eye(13)
+    res = gpu_riccati(torch, A, B, Q, R, QN, off, c, q, r, qN)
+    K, kff, P = riccati_batched(off, A.astype(np.float64), B.astype(np.float64), Q, R, QN, c, q, r, qN)
+    eK, ek, eP = rel_max(res["K"], K), rel_max(res["kff"], kff), rel_max(res["P"], P)
+    print(f"  rel err K {eK:.2e} kff {ek:.2e} P {eP:.2e}")
+    assert eK < 1e-9 and ek < 1e-9 and eP < 1e-9
+
+
+def test_gains_match_bruteforce_kkt(torch):
+    N = 3
+    A, B, rng = random_lq(N, 2)
+    c = rng.normal(size=(N, 13)) * 0.1
+    Q = np.eye(13); R = 0.1 * np.eye(4); QN = np.eye(13)
+    res = gpu_riccati(torch, A, B, Q, R, QN, np.array([0, N], np.int32), c=c)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    du0, _ = kkt_bruteforce(A64, B64, Q, R, QN, np.zeros(13), c)
+    np.testing.assert_allclose(res["kff"][0], du0[0], atol=1e-10)
+    for j in range(13):
+        e = np.zeros(13); e[j] = 1
+        du, _ = kkt_bruteforce(A64, B64, Q, R, QN, e, c)
+        np.testing.assert_allclose(res["K"][0] @ e + res["kff"][0], du[0], atol=1e-10)
+
+
+def test_linearized_c3_batch(torch):
+    """Gains of the benchmarked workload's linearisation (4096 instances, ragged horizons)."""
+    import paper_2203_07747_amd as rtn
+    cfg, off, x, u, Ws, bs = config_workload("c3")
+    m = rtn.Model(Ws, bs)
+    lin = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), m, "bf16", cfg.dt, offsets=off)
+    Q = np.eye(13); R = 0.1 * np.eye(4)
+    out = rtn.riccati(lin["A"], lin["B"], Q, R, Q, offsets=off, want_P=False)
+    torch.cuda.synchronize()
+    A, B = lin["A"].cpu().numpy(), lin["B"].cpu().numpy()
+    K = out["K"].cpu().numpy()
+    assert np.all(np.isfinite(K))
+    sel = np.random.default_rng(3).choice(len(off) - 1, 40, replace=False)
+    for i in sel:
+        a, b = off[i], off[i + 1]
+        Ko, ko, _ = riccati_batched(np.array([0, b - a]), A[a:b].astype(np.float64), B[a:b].astype(np.float64), Q, R, Q)
+        assert rel_max(K[a:b], Ko) < 1e-9
+    m.close()
+
+
+def test_indefinite_input_hessian_gives_nan(torch):
+    A, B, _ = random_lq(4, 3)
+    res = gpu_riccati(torch, A, B, np.eye(13), -np.eye(4), np.zeros((13, 13)), np.array([0, 4], np.int32))
+    assert np.all(np.isnan(res["K"][3])) and np.all(np.isnan(res["kff"][3]))
+
+
+def test_empty_and_single_node(torch):
+    A, B, _ = random_lq(5, 5)
+    off = np.array([0, 1, 2, 3, 4, 5], np.int32)
+    Q = np.eye(13); R = np.eye(4)
+    res = gpu_riccati(torch, A, B, Q, R, Q, off)
+    K, kff, P = riccati_batched(off, A.astype(np.float64), B.astype(np.float64), Q, R, Q)
+    assert rel_max(res["K"], K) < 1e-12

@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-compare", action="store_true", help="skip the other-precision comparison runs")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the latency, Riccati and training side measurements")
     return p.parse_args()
 
 
@@ -94,6 +96,41 @@ def cpu_baseline(cfg, x, u, Ws, bs, gpu_out, seconds):
            "sample": f"first {n_sample} nodes of the workload, fp64 NumPy oracle, repeated for "
                      f"{elapsed:.1f} s ({done} node linearisations)"}
     return cpu, errs
+
+
+def extras(torch, rtn, lin_out, off, stream):
+    """Side measurements: single-instance latency (the paper's real-time regime), the fp64
+    Riccati solve of this workload's A_k, B_k, and one training step of the residual."""
+    from workload import TRAIN, xavier_params as xp
+    res = {}
+    for key in ("c1", "c2"):
+        cfg, o, x, u, Ws, bs = config_workload(key)
+        m = rtn.Model(Ws, bs)
+        xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
+        out = {}
+        f = lambda: rtn.linearize(xt, ut, m, "fp32", cfg.dt, offsets=o, out=out, stream=stream)
+        ms, wall = time_steps(torch, f, 200, 20, stream)
+        res[f"latency_{key}"] = {"workload": cfg.name, "us_per_call": ms * 1e3, "host_us_per_call": wall * 1e3}
+        m.close()
+    Q = np.eye(13); R = 0.1 * np.eye(4)
+    rout = {}
+    f = lambda: rtn.riccati(lin_out["A"], lin_out["B"], Q, R, Q, offsets=off, out=rout, stream=stream)
+    ms, _ = time_steps(torch, f, 10, 2, stream)
+    res["riccati_fp64"] = {"ms_per_call": ms, "instances": int(len(off) - 1),
+                           "nodes_per_s": float(off[-1]) / (ms * 1e-3)}
+    Ws, bs = xp(TRAIN["n_hidden"], TRAIN["width"], seed=0)
+    m = rtn.Model(Ws, bs)
+    B = TRAIN["batch"]
+    g = torch.Generator(device="cuda").manual_seed(0)
+    z = torch.randn((B, 14), device="cuda", generator=g)
+    t = torch.randn((B, 6), device="cuda", generator=g)
+    loss = torch.empty((1,), device="cuda")
+    f = lambda: m.train_step(z, t, lr=TRAIN["lr"], prec="bf16", loss=loss, stream=stream)
+    ms, _ = time_steps(torch, f, 20, 3, stream)
+    W = sum(w.size for w in Ws)
+    res["train_step_bf16"] = {"ms_per_step": ms, "batch": B, "tflops": 6 * W * B / (ms * 1e-3) / 1e12}
+    m.close()
+    return res
 
 
 def main():
@@ -176,6 +213,8 @@ def main():
             cmp[p] = {"value": n / (m2 * 1e-3), "ms_per_step": m2, "steps": k2,
                       "mfma_frac": n * (f_fwd + f_rev) / (m2 * 1e-3) / 1e12 / PEAK_TFLOPS[p]}
         result["other_precisions_same_workload"] = cmp
+    if not args.no_extras:
+        result["extras"] = extras(torch, rtn, out, off, stream)
     if not args.no_cpu:
         cpu, errs = cpu_baseline(cfg, x, u, Ws, bs, gpu_out, args.cpu_seconds)
         result["cpu_baseline"] = cpu

@@ -126,6 +126,63 @@ class Model:
               "rtn_model_get_scales")
         return out
 
+    # ---- training (Sec. VII): the library's own forward/backward kernels -------------
+    def forward_batch(self, z, prec: str = "bf16", stream=None):
+        """Network output y [B,6] for inputs z [B,14]; stashes what backward_batch needs."""
+        torch = _torch()
+        B = z.shape[0]
+        y = torch.empty((B, 6), dtype=torch.float32, device=z.device)
+        check(load().rtn_mlp_forward(self.handle, PREC[prec], B, _dev(z, torch.float32, (B, 14), "z"),
+                                     _dev(y, torch.float32, (B, 6), "y"), _stream(stream)), "rtn_mlp_forward")
+        return y
+
+    def backward_batch(self, dy, want_din: bool = True, stream=None):
+        """Add dL/dparams for upstream dy [B,6] to the gradient buffer; return dL/dz [B,14]."""
+        torch = _torch()
+        B = dy.shape[0]
+        din = torch.empty((B, 14), dtype=torch.float32, device=dy.device) if want_din else None
+        check(load().rtn_mlp_backward(self.handle, B, _dev(dy.contiguous(), torch.float32, (B, 6), "dy"),
+                                      _dev(din, torch.float32, (B, 14), "din") if din is not None else None,
+                                      _stream(stream)), "rtn_mlp_backward")
+        return din
+
+    def zero_grad(self, stream=None) -> None:
+        check(load().rtn_model_zero_grad(self.handle, _stream(stream)), "rtn_model_zero_grad")
+
+    def get_grad(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(load().rtn_model_get_grad(self.handle, out.ctypes.data_as(ctypes.c_void_p)), "rtn_model_get_grad")
+        return out
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> None:
+        check(load().rtn_adam_step(self.handle, lr, beta1, beta2, eps, _stream(stream)), "rtn_adam_step")
+
+    def train_step(self, z, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, prec: str = "bf16",
+                   loss=None, stream=None):
+        """Fused forward + MSE + backward + Adam; returns the (device) loss before the update."""
+        torch = _torch()
+        B = z.shape[0]
+        if loss is None:
+            loss = torch.empty((1,), dtype=torch.float32, device=z.device)
+        check(load().rtn_train_step(self.handle, PREC[prec], B, _dev(z, torch.float32, (B, 14), "z"),
+                                    _dev(target, torch.float32, (B, 6), "target"), lr, beta1, beta2, eps,
+                                    _dev(loss, torch.float32, (1,), "loss"), _stream(stream)), "rtn_train_step")
+        return loss
+
+    def get_adam(self):
+        m = np.empty(self.n_params, dtype=np.float32)
+        v = np.empty(self.n_params, dtype=np.float32)
+        t = ctypes.c_int64()
+        check(load().rtn_model_get_adam(self.handle, m.ctypes.data_as(ctypes.c_void_p),
+                                        v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)), "rtn_model_get_adam")
+        return m, v, t.value
+
+    def set_adam(self, m, v, step: int) -> None:
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        check(load().rtn_model_set_adam(self.handle, m.ctypes.data_as(ctypes.c_void_p),
+                                        v.ctypes.data_as(ctypes.c_void_p), step), "rtn_model_set_adam")
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             load().rtn_model_destroy(self._h)
@@ -192,9 +249,14 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
     dev = A.device
     if out is None:
         out = {}
-    K = out.setdefault("K", torch.empty((n, 4, 13), dtype=torch.float64, device=dev))
-    kff = out.setdefault("kff", torch.empty((n, 4), dtype=torch.float64, device=dev))
-    P = out.setdefault("P", torch.empty((n, 13, 13), dtype=torch.float64, device=dev)) if want_P else None
+    def get(name, shape):
+        t = out.get(name)
+        if t is None:
+            t = out[name] = torch.empty(shape, dtype=torch.float64, device=dev)
+        return t
+    K = get("K", (n, 4, 13))
+    kff = get("kff", (n, 4))
+    P = get("P", (n, 13, 13)) if want_P else None
     if offsets is None:
         n_inst, off_ptr = 1, None
     else:
@@ -216,3 +278,23 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
                              _dev(P, f64, (n, 13, 13), "P") if P is not None else None,
                              _stream(stream)), "rtn_riccati")
     return out
+
+
+def mlp_function():
+    """torch.autograd.Function over the library's forward/backward kernels.
+
+    ``MLP.apply(z, model, prec)`` returns y [B,6]; its backward returns dL/dz and
+    adds dL/dparams to the model's gradient buffer (step with model.adam_step)."""
+    torch = _torch()
+
+    class MLP(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, z, model, prec="bf16"):
+            ctx.model = model
+            return model.forward_batch(z.contiguous(), prec)
+
+        @staticmethod
+        def backward(ctx, dy):
+            return ctx.model.backward_batch(dy.contiguous(), want_din=True), None, None
+
+    return MLP

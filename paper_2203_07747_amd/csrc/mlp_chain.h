@@ -33,10 +33,12 @@ hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int tra
 hipError_t launch_amax(const float* a, long n, float* out, hipStream_t st);
 hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st);
 hipError_t launch_mlp_forward(int prec, int H, const NetView& net, int n, const float* x, const float* u,
-                              const float* zin, void* stash, float* y, float* amax, hipStream_t st);
+                              const float* zin, void* stash, float* y, float* amax, hipStream_t st,
+                              float* hsave = nullptr);
 hipError_t launch_mlp_reverse(int prec, int H, const NetView& net, int n, const void* stash, float* J, float* amax,
                               hipStream_t st);
 int stash_elem_bytes(int prec);
+int num_cu();  // compute units of the current device (cached after the first call)
 hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st);
 
 struct QuadConst {
@@ -48,5 +50,13 @@ hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float
 hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const double* R, const double* QN,
                           const float* A, const float* B, const double* c, const double* q, const double* r,
                           const double* qN, double* K, double* kff, double* P, hipStream_t st);
+
+hipError_t launch_gemm_strided(int prec, int M, int N, int K, const float* A, long sAm, long sAk, const float* B,
+                               long sBk, long sBn, float* C, long sCm, int accumulate, const void* gate,
+                               int gate_is_f32, int ldg, hipStream_t st);
+hipError_t launch_mse(int nel, const float* y, const float* t, float* dy, float* loss, hipStream_t st);
+hipError_t launch_colsum(int rows, int cols, const float* d, float* db, hipStream_t st);
+hipError_t launch_adam(long n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, hipStream_t st);
 
 }  // namespace rtn

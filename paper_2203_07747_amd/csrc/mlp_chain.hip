@@ -306,7 +306,7 @@ template <int P, int H>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H>::NW * kWave)))
 mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* __restrict__ u,
                   const float* __restrict__ zin, typename StashT<P>::type* __restrict__ stash,
-                  float* __restrict__ y, float* __restrict__ amax) {
+                  float* __restrict__ y, float* __restrict__ amax, float* __restrict__ hsave) {
   constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
   using C = Chain<P, H, R, NW>;
   using elem = typename C::elem;
@@ -390,6 +390,13 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
             for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(h[vi]));
           }
           if (row < n) store16<S>(st + (size_t)row * H + mt * 32 + g * 16, sp);
+          if (hsave && row < n) {  // training: h_l in natural feature order
+            float* hd = hsave + ((size_t)layer * n + row) * H + mt * 32 + g * 4;
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4)
+              reinterpret_cast<float4*>(hd + q4 * 8)[0] =
+                  make_float4(h[4 * q4], h[4 * q4 + 1], h[4 * q4 + 2], h[4 * q4 + 3]);
+          }
           C::put_operand(lds, r, mt, lane, h, inv_next);
         }
       }
@@ -700,7 +707,7 @@ hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st) {
 }
 
 static int g_num_cu = 0;
-static int num_cu() {
+int num_cu() {
   if (!g_num_cu) {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -713,12 +720,13 @@ static int num_cu() {
 
 template <int P, int H>
 static hipError_t fwd_impl(const NetView& net, int n, const float* x, const float* u, const float* zin, void* stash,
-                           float* y, float* amax, hipStream_t st, int grid_cap) {
+                           float* y, float* amax, float* hsave, hipStream_t st, int grid_cap) {
   constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
   int blocks = (n + R - 1) / R;
   int grid = blocks < grid_cap ? blocks : grid_cap;
   if (grid <= 0) return hipSuccess;
-  mlp_forward_chain<P, H><<<grid, NW * kWave, 0, st>>>(net, n, x, u, zin, (typename StashT<P>::type*)stash, y, amax);
+  mlp_forward_chain<P, H><<<grid, NW * kWave, 0, st>>>(net, n, x, u, zin, (typename StashT<P>::type*)stash, y, amax,
+                                                        hsave);
   return hipGetLastError();
 }
 
@@ -744,11 +752,11 @@ static hipError_t rev_impl(const NetView& net, int n, const void* stash, float* 
   }
 
 hipError_t launch_mlp_forward(int prec, int H, const NetView& net, int n, const float* x, const float* u,
-                              const float* zin, void* stash, float* y, float* amax, hipStream_t st) {
+                              const float* zin, void* stash, float* y, float* amax, hipStream_t st, float* hsave) {
   const int cap = 2 * num_cu();
-  if (prec == P_FP32) { RTN_DISPATCH_H(P_FP32, fwd_impl, net, n, x, u, zin, stash, y, amax, st, cap) }
-  if (prec == P_BF16) { RTN_DISPATCH_H(P_BF16, fwd_impl, net, n, x, u, zin, stash, y, amax, st, cap) }
-  RTN_DISPATCH_H(P_FP8, fwd_impl, net, n, x, u, zin, stash, y, amax, st, cap)
+  if (prec == P_FP32) { RTN_DISPATCH_H(P_FP32, fwd_impl, net, n, x, u, zin, stash, y, amax, hsave, st, cap) }
+  if (prec == P_BF16) { RTN_DISPATCH_H(P_BF16, fwd_impl, net, n, x, u, zin, stash, y, amax, hsave, st, cap) }
+  RTN_DISPATCH_H(P_FP8, fwd_impl, net, n, x, u, zin, stash, y, amax, hsave, st, cap)
 }
 
 hipError_t launch_mlp_reverse(int prec, int H, const NetView& net, int n, const void* stash, float* J, float* amax,

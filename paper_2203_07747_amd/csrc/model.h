@@ -33,6 +33,26 @@ struct Model {
   size_t stash_bytes = 0;
   float* tmp = nullptr;
   size_t tmp_bytes = 0;
+  // training workspace (grown on demand): stash and activations of the last
+  // rtn_mlp_forward, its batch and precision, output, dL/dy, two delta buffers
+  void* tstash = nullptr;
+  float* hsave = nullptr;
+  float* ty = nullptr;
+  float* tdy = nullptr;
+  float* tdelta[2] = {nullptr, nullptr};
+  const float* tin = nullptr;
+  int64_t tcap = 0;
+  int32_t tbatch = 0, tprec = -1;
+  // captured rtn_linearize launch sequences, replayed on the caller's stream
+  struct GraphEntry {
+    uint64_t key[16];
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t cap_stream = nullptr;
+  void drop_graphs();
   std::vector<void*> allocs;
 
   ~Model();
@@ -42,6 +62,7 @@ struct Model {
   rtn_status repack(hipStream_t st);
   rtn_status ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st);
   NetView view(int prec) const;
+  rtn_status ensure_train_workspace(int64_t batch, hipStream_t st);
   int64_t layer_fan_in(int l) const;
   int64_t layer_fan_out(int l) const;
   static int elem_bytes(int prec);

@@ -33,6 +33,11 @@ hipEvent_t get_event() {
 
 }  // namespace
 
+bool profiling_on() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_on;
+}
+
 ProfScope::ProfScope(const char* name, hipStream_t st) : st_(st) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on || g_recs.size() >= 65536) return;

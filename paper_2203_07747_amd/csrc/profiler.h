@@ -17,4 +17,6 @@ class ProfScope {
   hipStream_t st_ = nullptr;
 };
 
+bool profiling_on();
+
 }  // namespace rtn

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -74,7 +75,14 @@ static int64_t count_params(const rtn_mlp_desc& d) {
 }
 
 rtn::Model::~Model() {
+  drop_graphs();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void* p : allocs) (void)hipFree(p);
+}
+
+void rtn::Model::drop_graphs() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
 }
 
 rtn_status rtn::Model::alloc(void** p, size_t bytes) {
@@ -95,6 +103,7 @@ void rtn::Model::release(void* p) {
 }
 
 rtn_status rtn::Model::init(const rtn_mlp_desc& d) {
+  (void)num_cu();  // device query outside any stream capture
   desc = d;
   L = d.n_hidden;
   H = d.width;
@@ -174,6 +183,7 @@ rtn_status rtn::Model::ensure_workspace(int64_t n, int64_t nrow_train, hipStream
   (void)nrow_train;
   const size_t need = (size_t)L * n * H * 4;  // fp32 stash is the largest
   if (need > stash_bytes) {
+    drop_graphs();
     if (stash) {
       HIP_TRY(hipStreamSynchronize(st));
       release(stash);
@@ -186,6 +196,7 @@ rtn_status rtn::Model::ensure_workspace(int64_t n, int64_t nrow_train, hipStream
   }
   const size_t need_y = (size_t)n * (kDout + kDout * kDin) * 4;
   if (need_y > tmp_bytes) {
+    drop_graphs();
     if (tmp) {
       HIP_TRY(hipStreamSynchronize(st));
       release(tmp);
@@ -347,31 +358,85 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
     return fail(RTN_EINVAL, "RTN_FP8 needs rtn_model_calibrate first");
   hipStream_t st = (hipStream_t)stream;
   QuadConst qc{quad->mass, quad->Jx, quad->Jy, quad->Jz, quad->arm, quad->c_tau, quad->g};
-  const float* fD_in = nullptr;
-  const float* JD_in = nullptr;
-  if (m) {
-    if ((s = m->ensure_workspace(n_nodes, 0, st))) return s;
-    float* y = f_D ? f_D : m->tmp;
-    float* J = J_D ? J_D : m->tmp + (size_t)n_nodes * kDout;
-    NetView v = m->view(prec);
-    {
-      ProfScope ps("mlp_forward_chain", st);
-      HIP_TRY(launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, st));
-    }
-    {
-      ProfScope ps("mlp_reverse_chain", st);
-      HIP_TRY(launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, st));
-    }
-    fD_in = y;
-    JD_in = J;
-  } else {
+  if (!m) {
     if (f_D) HIP_TRY(hipMemsetAsync(f_D, 0, (size_t)n_nodes * kDout * 4, st));
     if (J_D) HIP_TRY(hipMemsetAsync(J_D, 0, (size_t)n_nodes * kDout * kDin * 4, st));
-  }
-  {
     ProfScope ps("rk4_linearize", st);
-    HIP_TRY(launch_rk4_linearize(n_nodes, qc, dt, x, u, fD_in, JD_in, x_next, A, B, status, st));
+    HIP_TRY(launch_rk4_linearize(n_nodes, qc, dt, x, u, nullptr, nullptr, x_next, A, B, status, st));
+    return RTN_OK;
   }
+  if ((s = m->ensure_workspace(n_nodes, 0, st))) return s;
+  float* y = f_D ? f_D : m->tmp;
+  float* J = J_D ? J_D : m->tmp + (size_t)n_nodes * kDout;
+  const NetView v = m->view(prec);
+  auto enqueue = [&](hipStream_t q) -> hipError_t {
+    hipError_t e;
+    {
+      ProfScope ps("mlp_forward_chain", q);
+      if ((e = launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, q)) != hipSuccess) return e;
+    }
+    {
+      ProfScope ps("mlp_reverse_chain", q);
+      if ((e = launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, q)) != hipSuccess) return e;
+    }
+    ProfScope ps("rk4_linearize", q);
+    return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q);
+  };
+  // The three launches are captured once per distinct argument set into a HIP
+  // graph (on a private stream) and replayed as one graph launch on the caller's
+  // stream.  Profiling, or RTN_NO_GRAPH=1, uses plain launches.
+  static const bool no_graph = [] {
+    const char* e = getenv("RTN_NO_GRAPH");
+    return e && e[0] == '1';
+  }();
+  if (no_graph || profiling_on()) {
+    HIP_TRY(enqueue(st));
+    return RTN_OK;
+  }
+  uint32_t qbits[7];
+  memcpy(qbits, &qc, sizeof qbits);
+  uint32_t dtb;
+  memcpy(&dtb, &dt, 4);
+  const uint64_t key[16] = {(uint64_t)prec | ((uint64_t)n_nodes << 8), (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)u,
+                            (uint64_t)(uintptr_t)x_next, (uint64_t)(uintptr_t)A, (uint64_t)(uintptr_t)B,
+                            (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)J, (uint64_t)(uintptr_t)status,
+                            (uint64_t)(uintptr_t)m->stash, ((uint64_t)qbits[0] << 32) | qbits[1],
+                            ((uint64_t)qbits[2] << 32) | qbits[3], ((uint64_t)qbits[4] << 32) | qbits[5],
+                            ((uint64_t)qbits[6] << 32) | dtb, 0, 0};
+  Model::GraphEntry* hit = nullptr;
+  for (auto& g : m->graphs)
+    if (!memcmp(g.key, key, sizeof key)) hit = &g;
+  if (!hit) {
+    if (!m->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue(m->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(m->cap_stream, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(e, "capturing rtn_linearize");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (m->graphs.size() >= 8) {  // bounded cache: evict the least recently used
+      size_t old = 0;
+      for (size_t i = 1; i < m->graphs.size(); ++i)
+        if (m->graphs[i].last_use < m->graphs[old].last_use) old = i;
+      (void)hipGraphExecDestroy(m->graphs[old].exec);
+      m->graphs.erase(m->graphs.begin() + old);
+    }
+    Model::GraphEntry g;
+    memcpy(g.key, key, sizeof key);
+    g.exec = exec;
+    g.last_use = 0;
+    m->graphs.push_back(g);
+    hit = &m->graphs.back();
+  }
+  hit->last_use = ++m->graph_clock;
+  HIP_TRY(hipGraphLaunch(hit->exec, st));
   return RTN_OK;
 }
 
@@ -419,3 +484,178 @@ extern "C" rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, i
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
   return RTN_OK;
 }
+
+// ---------------------------------------------------------------------------
+// training
+
+rtn_status rtn::Model::ensure_train_workspace(int64_t batch, hipStream_t st) {
+  if (batch <= tcap) return RTN_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  void* old[] = {tstash, hsave, ty, tdy, tdelta[0], tdelta[1]};
+  for (void* p : old) release(p);
+  tstash = nullptr;
+  hsave = ty = tdy = tdelta[0] = tdelta[1] = nullptr;
+  tcap = 0;
+  rtn_status s;
+  if ((s = alloc(&tstash, (size_t)L * batch * H * 4))) return s;
+  if ((s = alloc((void**)&hsave, (size_t)L * batch * H * 4))) return s;
+  if ((s = alloc((void**)&ty, (size_t)batch * kDout * 4))) return s;
+  if ((s = alloc((void**)&tdy, (size_t)batch * kDout * 4))) return s;
+  for (int i = 0; i < 2; ++i)
+    if ((s = alloc((void**)&tdelta[i], (size_t)batch * H * 4))) return s;
+  tcap = batch;
+  return RTN_OK;
+}
+
+static rtn_status train_forward(Model* m, int32_t prec, int32_t batch, const float* in, hipStream_t st) {
+  rtn_status s = m->ensure_train_workspace(batch, st);
+  if (s) return s;
+  NetView v = m->view(prec);
+  ProfScope ps("mlp_forward_chain(train)", st);
+  HIP_TRY(launch_mlp_forward(prec, m->H, v, batch, nullptr, nullptr, in, m->tstash, m->ty, nullptr, st, m->hsave));
+  m->tin = in;
+  m->tbatch = batch;
+  m->tprec = prec;
+  return RTN_OK;
+}
+
+// Add dL/dparams of the last forward for upstream gradient dy [batch][6]; din optional.
+static rtn_status train_backward(Model* m, const float* dy, float* din, hipStream_t st) {
+  const int B = m->tbatch, H = m->H, L = m->L, prec = m->tprec;
+  const int gate_f32 = prec == P_FP32 ? 1 : 0;
+  const size_t sb = (size_t)(prec == P_FP32 ? 4 : 2);
+  const char* stash = static_cast<const char*>(m->tstash);
+  ProfScope ps("train_backward", st);
+  // output layer W_{L+1} (6 x H): dW = dy^T h_L, db = sum dy, delta_L = (dy W) * act'(a_L)
+  HIP_TRY(launch_gemm_strided(prec, kDout, H, B, dy, 1, kDout, m->hsave + (size_t)(L - 1) * B * H, H, 1,
+                              m->grad + m->w_off[L], H, 1, nullptr, 1, 0, st));
+  HIP_TRY(launch_colsum(B, kDout, dy, m->grad + m->b_off[L], st));
+  HIP_TRY(launch_gemm_strided(prec, B, H, kDout, dy, kDout, 1, m->params + m->w_off[L], H, 1, m->tdelta[0], H, 0,
+                              stash + (size_t)(L - 1) * B * H * sb, gate_f32, H, st));
+  int cur = 0;
+  for (int l = L - 1; l >= 0; --l) {  // weight W_{l+1}: fan_out H, fan_in (l == 0 ? 14 : H)
+    const int fi = l == 0 ? kDin : H;
+    const float* hin = l == 0 ? m->tin : m->hsave + (size_t)(l - 1) * B * H;
+    const float* d = m->tdelta[cur];
+    HIP_TRY(launch_gemm_strided(prec, H, fi, B, d, 1, H, hin, fi, 1, m->grad + m->w_off[l], fi, 1, nullptr, 1, 0, st));
+    HIP_TRY(launch_colsum(B, H, d, m->grad + m->b_off[l], st));
+    if (l > 0) {
+      HIP_TRY(launch_gemm_strided(prec, B, H, H, d, H, 1, m->params + m->w_off[l], H, 1, m->tdelta[cur ^ 1], H, 0,
+                                  stash + (size_t)(l - 1) * B * H * sb, gate_f32, H, st));
+      cur ^= 1;
+    } else if (din) {
+      HIP_TRY(launch_gemm_strided(prec, B, kDin, H, d, H, 1, m->params + m->w_off[0], kDin, 1, din, kDin, 0, nullptr,
+                                  1, 0, st));
+    }
+  }
+  return RTN_OK;
+}
+
+static rtn_status adam_update(Model* m, float lr, float b1, float b2, float eps, hipStream_t st) {
+  m->adam_step += 1;
+  const double t = (double)m->adam_step;
+  const float bc1 = (float)(1.0 - std::pow((double)b1, t));
+  const float bc2 = (float)(1.0 - std::pow((double)b2, t));
+  {
+    ProfScope ps("adam", st);
+    HIP_TRY(launch_adam(m->n_params, m->params, m->grad, m->adam_m, m->adam_v, lr, b1, b2, eps, bc1, bc2, st));
+  }
+  return m->repack(st);
+}
+
+static rtn_status check_train_prec(int32_t prec) {
+  if (prec != RTN_FP32 && prec != RTN_BF16) return fail(RTN_ENOTSUP, "training supports RTN_FP32 and RTN_BF16 (got %d)", prec);
+  return RTN_OK;
+}
+
+static rtn_status check_adam(float lr, float b1, float b2, float eps) {
+  if (!(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+    return fail(RTN_EINVAL, "Adam needs lr > 0, 0 <= beta1, beta2 < 1, eps > 0");
+  return RTN_OK;
+}
+
+extern "C" {
+
+rtn_status rtn_mlp_forward(rtn_model* model, int32_t prec, int32_t batch, const float* in, float* out, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  rtn_status s = check_train_prec(prec);
+  if (s) return s;
+  if (batch <= 0) return fail(RTN_EINVAL, "batch must be >= 1 (got %d)", batch);
+  if (!in || !out) return fail(RTN_EINVAL, "in and out must be device pointers");
+  Model* m = reinterpret_cast<Model*>(model);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = train_forward(m, prec, batch, in, st))) return s;
+  HIP_TRY(hipMemcpyAsync(out, m->ty, (size_t)batch * kDout * 4, hipMemcpyDeviceToDevice, st));
+  return RTN_OK;
+}
+
+rtn_status rtn_mlp_backward(rtn_model* model, int32_t batch, const float* dout, float* din, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  Model* m = reinterpret_cast<Model*>(model);
+  if (m->tprec < 0 || m->tbatch != batch)
+    return fail(RTN_EINVAL, "rtn_mlp_backward needs a preceding rtn_mlp_forward with the same batch (%d)", batch);
+  if (!dout) return fail(RTN_EINVAL, "dout must be a device pointer");
+  return train_backward(m, dout, din, (hipStream_t)stream);
+}
+
+rtn_status rtn_model_zero_grad(rtn_model* model, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  Model* m = reinterpret_cast<Model*>(model);
+  HIP_TRY(hipMemsetAsync(m->grad, 0, m->n_params * 4, (hipStream_t)stream));
+  return RTN_OK;
+}
+
+rtn_status rtn_model_get_grad(rtn_model* model, float* grad_host) {
+  if (!model || !grad_host) return fail(RTN_EINVAL, "model and grad_host are required");
+  Model* m = reinterpret_cast<Model*>(model);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(grad_host, m->grad, m->n_params * 4, hipMemcpyDeviceToHost));
+  return RTN_OK;
+}
+
+rtn_status rtn_adam_step(rtn_model* model, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  rtn_status s = check_adam(lr, beta1, beta2, eps);
+  if (s) return s;
+  return adam_update(reinterpret_cast<Model*>(model), lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch, const float* in, const float* target,
+                          float lr, float beta1, float beta2, float eps, float* loss, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  rtn_status s = check_train_prec(prec);
+  if (s) return s;
+  if ((s = check_adam(lr, beta1, beta2, eps))) return s;
+  if (batch <= 0) return fail(RTN_EINVAL, "batch must be >= 1 (got %d)", batch);
+  if (!in || !target) return fail(RTN_EINVAL, "in and target must be device pointers");
+  Model* m = reinterpret_cast<Model*>(model);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipMemsetAsync(m->grad, 0, m->n_params * 4, st));
+  if ((s = train_forward(m, prec, batch, in, st))) return s;
+  HIP_TRY(launch_mse(batch * kDout, m->ty, target, m->tdy, loss, st));
+  if ((s = train_backward(m, m->tdy, nullptr, st))) return s;
+  return adam_update(m, lr, beta1, beta2, eps, st);
+}
+
+rtn_status rtn_model_get_adam(rtn_model* model, float* m_host, float* v_host, int64_t* step) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  Model* m = reinterpret_cast<Model*>(model);
+  HIP_TRY(hipDeviceSynchronize());
+  if (m_host) HIP_TRY(hipMemcpy(m_host, m->adam_m, m->n_params * 4, hipMemcpyDeviceToHost));
+  if (v_host) HIP_TRY(hipMemcpy(v_host, m->adam_v, m->n_params * 4, hipMemcpyDeviceToHost));
+  if (step) *step = m->adam_step;
+  return RTN_OK;
+}
+
+rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float* v_host, int64_t step) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL");
+  if (step < 0) return fail(RTN_EINVAL, "step must be >= 0");
+  Model* m = reinterpret_cast<Model*>(model);
+  HIP_TRY(hipDeviceSynchronize());
+  if (m_host) HIP_TRY(hipMemcpy(m->adam_m, m_host, m->n_params * 4, hipMemcpyHostToDevice));
+  if (v_host) HIP_TRY(hipMemcpy(m->adam_v, v_host, m->n_params * 4, hipMemcpyHostToDevice));
+  m->adam_step = step;
+  return RTN_OK;
+}
+
+}  // extern "C"

@@ -155,6 +155,17 @@ rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const rtn_quad* q
                          float* x_next, float* A, float* B,
                          float* f_D, float* J_D, uint8_t* status, void* stream);
 
+/* The exact ("naive") linearisation of Sec. IV-A, for comparison with
+ * rtn_linearize: the network and its Jacobian are evaluated at all four RK4
+ * stage points (N*E function and N*E*2 derivative evaluations) instead of once
+ * per node, and x_{k+1}, A_k, B_k are the exact derivatives of one RK4 step of
+ * f_F + f_D.  Arguments, layouts and errors as rtn_linearize (model required;
+ * no f_D / J_D / status outputs).  Uses model-owned workspace. */
+rtn_status rtn_linearize_exact(const rtn_model* model, int32_t prec, const rtn_quad* quad, float dt,
+                               int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                               const float* x, const float* u, float* x_next, float* A, float* B,
+                               void* stream);
+
 /* Feedback phase: backward Riccati recursion of the LQ problem
  *   min sum_k 1/2 [dx;du]^T blkdiag(Q,R) [dx;du] + q_k^T dx + r_k^T du
  *       + 1/2 dx_N^T Q_N dx_N + qN^T dx_N

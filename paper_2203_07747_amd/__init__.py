@@ -239,6 +239,33 @@ def linearize(x, u, model: Optional[Model] = None, prec: str = "fp32", dt: float
     return out
 
 
+def linearize_exact(x, u, model: Model, prec: str = "fp32", dt: float = 0.05, quad=None,
+                    offsets: Optional[np.ndarray] = None, out: Optional[Dict[str, object]] = None,
+                    stream=None) -> Dict[str, object]:
+    """rtn_linearize_exact: network and Jacobian at all four RK4 stage points (the naive
+    linearisation the paper's local approximation avoids).  Returns x_next, A, B."""
+    torch = _torch()
+    from workload import QUAD
+    q = quad_struct(quad if quad is not None else QUAD)
+    n = x.shape[0]
+    out = {} if out is None else out
+    for name, shape in (("x_next", (n, 13)), ("A", (n, 13, 13)), ("B", (n, 13, 4))):
+        if out.get(name) is None:
+            out[name] = torch.empty(shape, dtype=torch.float32, device=x.device)
+    if offsets is None:
+        n_inst, off_ptr = 1, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    check(load().rtn_linearize_exact(model.handle, PREC[prec], ctypes.byref(q), ctypes.c_float(dt), n_inst, off_ptr,
+                                     n, _dev(x, torch.float32, (n, 13), "x"), _dev(u, torch.float32, (n, 4), "u"),
+                                     _dev(out["x_next"], torch.float32, (n, 13), "x_next"),
+                                     _dev(out["A"], torch.float32, (n, 13, 13), "A"),
+                                     _dev(out["B"], torch.float32, (n, 13, 4), "B"), _stream(stream)),
+          "rtn_linearize_exact")
+    return out
+
+
 def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_P: bool = False,
             out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
     """rtn_riccati over device tensors A [n,13,13], B [n,13,4] (fp32); Q, R, QN host arrays (fp64).

@@ -46,6 +46,8 @@ SIGNATURES = {
     "rtn_linearize": (c_int32, [c_void_p, c_int32, P(Quad), c_float, c_int32, c_void_p, c_int32,
                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p]),
+    "rtn_linearize_exact": (c_int32, [c_void_p, c_int32, P(Quad), c_float, c_int32, c_void_p, c_int32,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rtn_riccati": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]),

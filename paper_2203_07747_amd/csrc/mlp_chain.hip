@@ -377,7 +377,7 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
           for (int vi = 0; vi < 16; ++vi) {
             const float a = acc[i][r][vi] * scale + bm[vi];
             if (net.act == 0) {
-              const float sg = 1.f / (1.f + __expf(-a));
+              const float sg = __builtin_amdgcn_rcpf(1.f + __expf(-a));
               h[vi] = a * sg;
               sp[vi] = sg * (1.f + a * (1.f - sg));
             } else {

@@ -53,6 +53,8 @@ struct Model {
   uint64_t graph_clock = 0;
   hipStream_t cap_stream = nullptr;
   void drop_graphs();
+  float* exact_ws = nullptr;  // exact linearisation: xs, kp, kacc [n][13]; dkp, dacc [n][17][13]
+  int64_t exact_cap = 0;
   std::vector<void*> allocs;
 
   ~Model();

@@ -659,3 +659,53 @@ rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float
 }
 
 }  // extern "C"
+
+extern "C" rtn_status rtn_linearize_exact(const rtn_model* model, int32_t prec, const rtn_quad* quad, float dt,
+                                          int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                                          const float* x, const float* u, float* x_next, float* A, float* B,
+                                          void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL (the exact linearisation needs a network)");
+  if (!quad) return fail(RTN_EINVAL, "quad is NULL");
+  if (!(dt > 0.f) || !std::isfinite(dt)) return fail(RTN_EINVAL, "dt must be positive and finite");
+  rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
+  if (s) return s;
+  if (prec != RTN_FP32 && prec != RTN_BF16 && prec != RTN_FP8) return fail(RTN_EINVAL, "unknown precision %d", prec);
+  if (n_nodes == 0) return RTN_OK;
+  if (!x || !u || !x_next || !A || !B) return fail(RTN_EINVAL, "x, u, x_next, A and B must be device pointers");
+  Model* m = const_cast<Model*>(reinterpret_cast<const Model*>(model));
+  if (prec == RTN_FP8 && !m->calibrated) return fail(RTN_EINVAL, "RTN_FP8 needs rtn_model_calibrate first");
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = m->ensure_workspace(n_nodes, 0, st))) return s;
+  if (n_nodes > m->exact_cap) {
+    HIP_TRY(hipStreamSynchronize(st));
+    m->release(m->exact_ws);
+    m->exact_ws = nullptr;
+    m->exact_cap = 0;
+    if ((s = m->alloc((void**)&m->exact_ws, (size_t)n_nodes * (3 * 13 + 2 * 17 * 13) * 4))) return s;
+    m->exact_cap = n_nodes;
+  }
+  const size_t n13 = (size_t)n_nodes * 13, n17 = (size_t)n_nodes * 17 * 13;
+  float* xs = m->exact_ws;
+  float* kp = xs + n13;
+  float* kacc = kp + n13;
+  float* dkp = kacc + n13;
+  float* dacc = dkp + n17;
+  float* y = m->tmp;
+  float* J = m->tmp + (size_t)n_nodes * kDout;
+  QuadConst qc{quad->mass, quad->Jx, quad->Jy, quad->Jz, quad->arm, quad->c_tau, quad->g};
+  const NetView v = m->view(prec);
+  for (int stage = 0; stage < 4; ++stage) {
+    const float* xin = stage == 0 ? x : xs;
+    {
+      ProfScope ps("mlp_forward_chain", st);
+      HIP_TRY(launch_mlp_forward(prec, m->H, v, n_nodes, xin, u, nullptr, m->stash, y, nullptr, st));
+    }
+    {
+      ProfScope ps("mlp_reverse_chain", st);
+      HIP_TRY(launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, st));
+    }
+    ProfScope ps("rk4_exact_stage", st);
+    HIP_TRY(launch_rk4_exact_stage(n_nodes, stage, qc, dt, x, u, y, J, xs, kp, kacc, dkp, dacc, x_next, A, B, st));
+  }
+  return RTN_OK;
+}

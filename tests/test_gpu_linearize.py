@@ -243,3 +243,27 @@ def test_graph_replays_match_eager(torch):
         for k in ("x_next", "A", "B", "f_D", "J_D"):
             assert torch.equal(out_g[k], eager[k]), (rep, k)
     m.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_exact_linearisation_matches_oracle(torch, prec, tol):
+    """rtn_linearize_exact (network at all four RK4 stage points) against the oracle's exact
+    variant, and its gap to the local approximation of eq. (4)."""
+    import paper_2203_07747_amd as rtn
+    from oracle.rk4 import linearize_exact
+    Ws, bs = xavier_params(3, 256, seed=4)
+    x, u = sample_nodes(300, seed=21)
+    m = rtn.Model(Ws, bs)
+    print(f"[gpu] linearize_exact n=300 prec={prec}", flush=True)
+    out = rtn.linearize_exact(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), m, prec, DT)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = linearize_exact(x, u, MLP(Ws, bs), DT)
+    for name, r in zip(("x_next", "A", "B"), ref):
+        e = rel(res[name], r).max()
+        print(f"  {name} max rel err {e:.2e}")
+        assert e <= tol
+    aff = linearize_affine(x, u, MLP(Ws, bs), DT)
+    gap = rel(aff[1], ref[1]).max()
+    print(f"  affine-vs-exact gap on A: {gap:.2e}")
+    m.close()

@@ -38,6 +38,23 @@ def flops_per_node(L: int, H: int, d_in: int = 14, d_out: int = 6):
     return fwd, rev
 
 
+def measured_traffic(config_key: str, kernel_prefix: str):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/linearize_<config>_*_hbm_traffic.json), only while the kernel source
+    is the one the counters were taken on; else None."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"linearize_{config_key}_*_hbm_traffic.json")):
+        rec = json.load(open(path))
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+            return None
+        for k, v in rec["per_launch"].items():
+            if k.split("::")[-1].startswith(kernel_prefix):
+                return v["read_bytes"] + v["write_bytes"]
+    return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -192,7 +209,8 @@ def main():
         "config": {"workload": cfg.name, "n_inst": int(len(off) - 1), "n_nodes": int(n),
                    "hidden_layers": L, "width": H, "dt": cfg.dt},
         "roofline": {"bound": "mfma", "kernel": "mlp_reverse_chain", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(args.config, "mlp_reverse_chain"),
                      "algorithmic_flops_per_launch": n * f_rev, "avg_launch_ms": rev_ms},
         "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms},
         "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,

@@ -33,11 +33,14 @@ namespace rtn {
 // wave's accumulators (H/32/NW M-tiles x R/32 row tiles x 16 floats) must fit its
 // registers: <= 128 with two waves per SIMD (8 waves), <= 192 with one wave per
 // SIMD (4 waves), where the accumulators live in AGPRs.
-template <int P, int H> struct ChainShape {
-  static constexpr bool ONE_PER_SIMD = P == P_BF16 && H == 512;
+template <int P, int H, bool REV = true> struct ChainShape {
+  // the reverse sweep keeps one wave per SIMD (big accumulator tile, staged act'
+  // rows); the forward pass, whose epilogue (SiLU) is transcendental-heavy, keeps
+  // two waves per SIMD so one wave's epilogue overlaps the other's matrix work
+  static constexpr bool ONE_PER_SIMD = REV && P == P_BF16 && H == 512;
   static constexpr int NW = ONE_PER_SIMD ? 4 : (H >= 256 ? 8 : H / 32);
   static constexpr int R = P == P_FP32 ? (H <= 256 ? 128 : (H == 512 ? 64 : 32))
-                         : P == P_BF16 ? (H <= 256 ? 128 : (H == 512 ? 96 : 64))
+                         : P == P_BF16 ? (H <= 256 ? 128 : (H == 512 ? (REV ? 96 : 64) : 64))
                                        : (H <= 256 ? 128 : 64);
 };
 
@@ -88,18 +91,19 @@ template <int P, int H, int R, int NW> struct Chain {
     __device__ inline frag operator()(int r, int s, int lane) const { return lds_frag(lds, r, s, lane, KS); }
   };
 
-  template <int NMT, int NSTEPS>
+  template <int NMT, int NSTEPS, int RING = 0>
   __device__ static inline void gemm(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int MTALL, int KS,
                                      int mt0, int s0, int rot, const elem* lds, int lane) {
-    gemm_src<NMT, NSTEPS>(acc, Wp, MTALL, mt0, s0, rot, LdsB{lds, KS}, lane);
+    gemm_src<NMT, NSTEPS, RING>(acc, Wp, MTALL, mt0, s0, rot, LdsB{lds, KS}, lane);
   }
 
-  template <int NMT, int NSTEPS, class BSrc>
+  // RING: bytes of weight fragments per lane in flight (0 = default for the wave count)
+  template <int NMT, int NSTEPS, int RING, class BSrc>
   __device__ static inline void gemm_src(f32x16 (&acc)[NMT][RT], const frag* __restrict__ Wp, int MTALL,
                                          int mt0, int s0, int rot, const BSrc& bsrc, int lane) {
     // ring depth: up to 4 steps, at most 128 (two waves per SIMD) or 256 (one wave
     // per SIMD) bytes of weight fragments per lane
-    constexpr int PD0 = (NW <= 4 ? 256 : 128) / (NMT * (int)sizeof(frag));
+    constexpr int PD0 = (RING ? RING : (NW <= 4 ? 256 : 128)) / (NMT * (int)sizeof(frag));
     constexpr int PD1 = PD0 < 1 ? 1 : (PD0 > 4 ? 4 : PD0);
     constexpr int PD = NSTEPS < PD1 ? NSTEPS : PD1;
     static_assert(NSTEPS % PD == 0, "K-steps must be a multiple of the prefetch depth");
@@ -303,11 +307,11 @@ __device__ inline float from_stash(uint16_t v) { return bf16_to_f32(v); }
 // ---------------------------------------------------------------------------
 // Forward chain: z_0 -> h_1..h_L (stash act'), y.
 template <int P, int H>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H>::NW * kWave)))
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, false>::NW * kWave)))
 mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* __restrict__ u,
                   const float* __restrict__ zin, typename StashT<P>::type* __restrict__ stash,
                   float* __restrict__ y, float* __restrict__ amax, float* __restrict__ hsave) {
-  constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
+  constexpr int NW = ChainShape<P, H, false>::NW, R = ChainShape<P, H, false>::R;
   using C = Chain<P, H, R, NW>;
   using elem = typename C::elem;
   using frag = typename C::frag;
@@ -355,8 +359,8 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
         C::template gemm<C::MTW, C::KS_1>(acc, reinterpret_cast<const frag*>(net.fw[0]), C::MT, C::KS_1, wave * C::MTW,
                                           0, blk, lds, lane);
       else
-        C::template gemm<C::MTW, C::KS_H>(acc, reinterpret_cast<const frag*>(net.fw[layer]), C::MT, C::KS_H,
-                                          wave * C::MTW, 0, blk, lds, lane);
+        C::template gemm<C::MTW, C::KS_H, (NW > 4 ? 64 : 0)>(acc, reinterpret_cast<const frag*>(net.fw[layer]), C::MT,
+                                                              C::KS_H, wave * C::MTW, 0, blk, lds, lane);
       __syncthreads();
       const float scale = P == P_FP8 ? dq[layer] * net.ascale[layer] : 1.f;
       const float inv_next = P == P_FP8 ? 1.f / net.ascale[layer + 1] : 1.f;
@@ -721,7 +725,7 @@ int num_cu() {
 template <int P, int H>
 static hipError_t fwd_impl(const NetView& net, int n, const float* x, const float* u, const float* zin, void* stash,
                            float* y, float* amax, float* hsave, hipStream_t st, int grid_cap) {
-  constexpr int NW = ChainShape<P, H>::NW, R = ChainShape<P, H>::R;
+  constexpr int NW = ChainShape<P, H, false>::NW, R = ChainShape<P, H, false>::R;
   int blocks = (n + R - 1) / R;
   int grid = blocks < grid_cap ? blocks : grid_cap;
   if (grid <= 0) return hipSuccess;

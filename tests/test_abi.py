@@ -111,3 +111,22 @@ def test_riccati_validation(lib):
     Rbad = R.copy(); Rbad[0, 0] = np.inf
     assert lib.rtn_riccati(1, None, 3, z, z, None, qp, Rbad.ctypes.data_as(ctypes.c_void_p), qp, None, None, None,
                            z, z, None, None) == RTN_EINVAL
+
+
+def test_training_and_exact_validation(lib):
+    z = ctypes.c_void_p(16)
+    assert lib.rtn_train_step(None, 1, 8, z, z, 1e-3, 0.9, 0.999, 1e-8, None, None) == RTN_EINVAL
+    assert lib.rtn_mlp_forward(None, 1, 8, z, z, None) == RTN_EINVAL
+    assert lib.rtn_mlp_backward(None, 8, z, None, None) == RTN_EINVAL
+    assert lib.rtn_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, None) == RTN_EINVAL
+    q = Quad(QUAD.mass, QUAD.Jx, QUAD.Jy, QUAD.Jz, QUAD.arm, QUAD.c_tau, QUAD.g)
+    assert lib.rtn_linearize_exact(None, 0, ctypes.byref(q), ctypes.c_float(0.05), 1, None, 4,
+                                   z, z, z, z, z, None) == RTN_EINVAL
+    assert b"needs a network" in lib.rtn_last_error()
+
+
+def test_profile_read_without_records(lib):
+    n = ctypes.c_int32(-1)
+    assert lib.rtn_profile_enable(0) == RTN_OK
+    assert lib.rtn_profile_read(None, 0, ctypes.byref(n)) == RTN_OK
+    assert n.value == 0

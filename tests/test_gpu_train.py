@@ -148,13 +148,16 @@ def test_trained_residual_beats_nominal_model(torch):
     B = TRAIN["batch"]
     g = torch.Generator(device="cuda").manual_seed(0)
     losses = []
+    first = None
     for epoch in range(6):
         perm = torch.randperm(n_train, device="cuda", generator=g)
         for i in range(0, n_train - B + 1, B):
             idx = perm[i:i + B]
             loss = m.train_step(z[idx].contiguous(), y[idx].contiguous(), lr=TRAIN["lr"], prec="bf16")
+            if first is None:
+                first = float(loss.item())
         losses.append(float(loss.item()))
-    print("  training loss per epoch:", [f"{v:.4f}" for v in losses])
+    print(f"  loss of the first batch {first:.4f}; last batch of each epoch:", [f"{v:.4f}" for v in losses])
     # held-out transitions: the plant's next state vs the linearisation's phi-bar
     xv, uv = sample_nodes(4096 * 20, seed=SEED_TRAIN + 7)
     xs, _ = make_transitions(xv, uv, dt, seed=SEED_TRAIN + 8)
@@ -165,6 +168,6 @@ def test_trained_residual_beats_nominal_model(torch):
     e_nom = np.linalg.norm(nom[:, 7:13] - xs[:, 7:13], axis=1).mean()
     e_lrn = np.linalg.norm(lrn[:, 7:13] - xs[:, 7:13], axis=1).mean()
     print(f"  mean next-state [v, w] error: nominal {e_nom:.4e}  trained {e_lrn:.4e}  ratio {e_lrn / e_nom:.3f}")
-    assert losses[-1] < 0.5 * losses[0]
+    assert losses[-1] < 0.25 * first
     assert e_lrn < 0.5 * e_nom
     m.close()

@@ -185,6 +185,23 @@ rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, int32_t n_no
                        const double* q, const double* r, const double* qN,
                        double* K, double* kff, double* P, void* stream);
 
+/* Forward pass of the LQ solution returned by rtn_riccati: the primal step of
+ * the QP of Sec. IV-A (the step the feedback phase applies, Sec. IV-B).  Per
+ * instance, from its initial deviation dx_0:
+ *   du_k = K_k dx_k + kff_k,   dx_{k+1} = A_k dx_k + B_k du_k + c_k,  k = 0..N_i-1.
+ *   offsets_host  as in rtn_linearize (NULL: one instance)
+ *   A, B, c       as in rtn_riccati (c nullable)
+ *   K, kff        device fp64 [n][4][13], [n][4] (from rtn_riccati)
+ *   dx0           device fp64 [n_inst][13]
+ * outputs (device fp64): du [n][4]; dx nullable [n][13] = dx_k at node k
+ * (dx_0 repeated at the first node); dxN nullable [n_inst][13] = the terminal
+ * deviation dx_{N_i}.  Errors: RTN_EINVAL on bad offsets or a missing required
+ * pointer; nothing is enqueued then. */
+rtn_status rtn_lq_rollout(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                          const float* A, const float* B, const double* c,
+                          const double* K, const double* kff, const double* dx0,
+                          double* dx, double* du, double* dxN, void* stream);
+
 /* Network forward pass over a batch (device in [batch][14] -> out [batch][6]),
  * stashing what rtn_mlp_backward needs in the model.  prec RTN_FP32 or RTN_BF16. */
 rtn_status rtn_mlp_forward(rtn_model* model, int32_t prec, int32_t batch,

@@ -119,3 +119,38 @@ def kkt_bruteforce(A, B, Q, R, QN, dx0, c=None, q=None, r=None, qN=None):
     du = np.stack([z[ui(k):ui(k) + nu] for k in range(N)])
     dx = np.stack([z[xi(k):xi(k) + nx] for k in range(N + 1)])
     return du, dx
+
+
+def lq_rollout(A, B, K, kff, dx0, c=None):
+    """Forward pass of the LQ solution of one instance (the primal step of the QP):
+    du_k = K_k dx_k + kff_k,  dx_{k+1} = A_k dx_k + B_k du_k + c_k  from dx_0 = dx0.
+
+    Returns du (N,4) and dx (N+1,13), which equal the QP's minimiser
+    (``kkt_bruteforce``) when K, kff come from ``riccati`` on the same data."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    N, nx, nu = B.shape
+    c = np.zeros((N, nx)) if c is None else np.asarray(c, dtype=np.float64)
+    dx = np.zeros((N + 1, nx))
+    du = np.zeros((N, nu))
+    dx[0] = dx0
+    for k in range(N):
+        du[k] = K[k] @ dx[k] + kff[k]
+        dx[k + 1] = A[k] @ dx[k] + B[k] @ du[k] + c[k]
+    return du, dx
+
+
+def lq_rollout_batched(offsets, A, B, K, kff, dx0, c=None):
+    """``lq_rollout`` per CSR instance.  dx0 (n_inst,13) -> du (n,4), dx (n,13) for
+    k = 0..N_i-1 and the terminal dx_N (n_inst,13)."""
+    offsets = np.asarray(offsets)
+    n = int(offsets[-1])
+    nx, nu = B.shape[1], B.shape[2]
+    du = np.zeros((n, nu))
+    dx = np.zeros((n, nx))
+    dxN = np.zeros((len(offsets) - 1, nx))
+    for i in range(len(offsets) - 1):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        ui, xi = lq_rollout(A[a:b], B[a:b], K[a:b], kff[a:b], dx0[i], None if c is None else c[a:b])
+        du[a:b], dx[a:b], dxN[i] = ui, xi[:-1], xi[-1]
+    return du, dx, dxN

@@ -307,6 +307,42 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
     return out
 
 
+def lq_rollout(A, B, K, kff, dx0, offsets=None, c=None, want_dx: bool = True,
+               out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
+    """rtn_lq_rollout: the primal step of the LQ solution from per-instance initial
+    deviations dx0 [n_inst,13] (fp64).  Returns du [n,4], and optionally dx [n,13] and
+    the terminal dxN [n_inst,13] (fp64 device tensors)."""
+    torch = _torch()
+    n = A.shape[0]
+    dev = A.device
+    if offsets is None:
+        n_inst, off_ptr = 1, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    if out is None:
+        out = {}
+    def get(name, shape):
+        t = out.get(name)
+        if t is None:
+            t = out[name] = torch.empty(shape, dtype=torch.float64, device=dev)
+        return t
+    f64 = torch.float64
+    du = get("du", (n, 4))
+    dx = get("dx", (n, 13)) if want_dx else None
+    dxN = get("dxN", (n_inst, 13)) if want_dx else None
+    check(load().rtn_lq_rollout(n_inst, off_ptr, n, _dev(A, torch.float32, (n, 13, 13), "A"),
+                                _dev(B, torch.float32, (n, 13, 4), "B"),
+                                _dev(c, f64, (n, 13), "c") if c is not None else None,
+                                _dev(K, f64, (n, 4, 13), "K"), _dev(kff, f64, (n, 4), "kff"),
+                                _dev(dx0, f64, (n_inst, 13), "dx0"),
+                                _dev(dx, f64, (n, 13), "dx") if dx is not None else None,
+                                _dev(du, f64, (n, 4), "du"),
+                                _dev(dxN, f64, (n_inst, 13), "dxN") if dxN is not None else None,
+                                _stream(stream)), "rtn_lq_rollout")
+    return out
+
+
 def mlp_function():
     """torch.autograd.Function over the library's forward/backward kernels.
 

@@ -51,6 +51,8 @@ SIGNATURES = {
     "rtn_riccati": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]),
+    "rtn_lq_rollout": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rtn_mlp_forward": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "rtn_mlp_backward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "rtn_model_zero_grad": (c_int32, [c_void_p, c_void_p]),

@@ -50,6 +50,9 @@ hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float
 hipError_t launch_rk4_exact_stage(int n, int stage, const QuadConst& q, float dt, const float* x, const float* u,
                                   const float* fD, const float* JD, float* xs, float* kp, float* kacc, float* dkp,
                                   float* dacc, float* xn, float* A, float* B, hipStream_t st);
+hipError_t launch_lq_rollout(int n_inst, const int* offsets, const float* A, const float* B, const double* c,
+                             const double* K, const double* kff, const double* dx0, double* dx, double* du,
+                             double* dxN, hipStream_t st);
 hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const double* R, const double* QN,
                           const float* A, const float* B, const double* c, const double* q, const double* r,
                           const double* qN, double* K, double* kff, double* P, hipStream_t st);

@@ -167,6 +167,54 @@ __global__ void __launch_bounds__(64) riccati_kernel(RiccatiArgs a) {
   }
 }
 
+// Forward pass of the LQ solution (the primal step of the same QP): from the
+// instance's initial deviation dx_0,
+//   du_k = K_k dx_k + kff_k,   dx_{k+1} = A_k dx_k + B_k du_k + c_k.
+// One 64-lane workgroup per instance; lane i < 13 owns state row i, lane i < 4
+// input row i; the deviation vector lives in LDS between the two half-steps.
+__global__ void __launch_bounds__(64)
+lq_rollout_kernel(const int* __restrict__ offsets, const float* __restrict__ A, const float* __restrict__ B,
+                  const double* __restrict__ c, const double* __restrict__ K, const double* __restrict__ kff,
+                  const double* __restrict__ dx0, double* __restrict__ dx, double* __restrict__ du,
+                  double* __restrict__ dxN) {
+  __shared__ double sx[NX], su[NU];
+  const int inst = blockIdx.x, t = threadIdx.x;
+  const int k0 = offsets[inst], k1 = offsets[inst + 1];
+  if (t < NX) sx[t] = dx0[(size_t)inst * NX + t];
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    if (t < NX && dx) dx[(size_t)k * NX + t] = sx[t];
+    if (t < NU) {
+      const double* Kr = K + ((size_t)k * NU + t) * NX;
+      double s = kff[(size_t)k * NU + t];
+      for (int j = 0; j < NX; ++j) s += Kr[j] * sx[j];
+      su[t] = s;
+      du[(size_t)k * NU + t] = s;
+    }
+    __syncthreads();
+    double nx = 0.0;
+    if (t < NX) {
+      const float* Ar = A + ((size_t)k * NX + t) * NX;
+      const float* Br = B + ((size_t)k * NX + t) * NU;
+      nx = c ? c[(size_t)k * NX + t] : 0.0;
+      for (int j = 0; j < NX; ++j) nx += (double)Ar[j] * sx[j];
+      for (int j = 0; j < NU; ++j) nx += (double)Br[j] * su[j];
+    }
+    __syncthreads();
+    if (t < NX) sx[t] = nx;
+    __syncthreads();
+  }
+  if (t < NX && dxN) dxN[(size_t)inst * NX + t] = sx[t];
+}
+
+hipError_t launch_lq_rollout(int n_inst, const int* offsets, const float* A, const float* B, const double* c,
+                             const double* K, const double* kff, const double* dx0, double* dx, double* du,
+                             double* dxN, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  lq_rollout_kernel<<<n_inst, 64, 0, st>>>(offsets, A, B, c, K, kff, dx0, dx, du, dxN);
+  return hipGetLastError();
+}
+
 hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const double* R, const double* QN,
                           const float* A, const float* B, const double* c, const double* q, const double* r,
                           const double* qN, double* K, double* kff, double* P, hipStream_t st) {

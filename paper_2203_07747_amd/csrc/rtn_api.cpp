@@ -485,6 +485,37 @@ extern "C" rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, i
   return RTN_OK;
 }
 
+extern "C" rtn_status rtn_lq_rollout(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                                     const float* A, const float* B, const double* c, const double* K,
+                                     const double* kff, const double* dx0, double* dx, double* du, double* dxN,
+                                     void* stream) {
+  rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
+  if (s) return s;
+  if (n_nodes == 0) return RTN_OK;
+  if (!A || !B || !K || !kff || !dx0) return fail(RTN_EINVAL, "A, B, K, kff and dx0 must be device pointers");
+  if (!du) return fail(RTN_EINVAL, "du must be a device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> off((size_t)n_inst + 1);
+  if (offsets_host) {
+    memcpy(off.data(), offsets_host, off.size() * 4);
+  } else {
+    off[0] = 0;
+    off[1] = n_nodes;
+  }
+  void* dev = nullptr;
+  hipError_t e = hipMallocAsync(&dev, off.size() * 4, st);
+  if (e != hipSuccess) return fail(RTN_ENOMEM, "hipMallocAsync(%zu bytes): %s", off.size() * 4, hipGetErrorString(e));
+  e = hipMemcpyAsync(dev, off.data(), off.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    ProfScope ps("lq_rollout", st);
+    e = launch_lq_rollout(n_inst, static_cast<const int*>(dev), A, B, c, K, kff, dx0, dx, du, dxN, st);
+  }
+  hipError_t e2 = hipFreeAsync(dev, st);
+  if (e != hipSuccess) return hip_fail(e, "rtn_lq_rollout");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return RTN_OK;
+}
+
 // ---------------------------------------------------------------------------
 // training
 

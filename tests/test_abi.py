@@ -113,6 +113,16 @@ def test_riccati_validation(lib):
                            z, z, None, None) == RTN_EINVAL
 
 
+def test_lq_rollout_validation(lib):
+    z = ctypes.c_void_p(16)
+    assert lib.rtn_lq_rollout(1, None, 0, None, None, None, None, None, None, None, None, None, None) == RTN_OK
+    assert lib.rtn_lq_rollout(1, None, 3, z, z, None, None, z, z, None, z, None, None) == RTN_EINVAL
+    assert lib.rtn_lq_rollout(1, None, 3, z, z, None, z, z, z, None, None, None, None) == RTN_EINVAL
+    off = np.array([0, 3, 2], dtype=np.int32)
+    assert lib.rtn_lq_rollout(2, off.ctypes.data_as(ctypes.c_void_p), 2, z, z, None, z, z, z, None, z, None,
+                              None) == RTN_EINVAL
+
+
 def test_training_and_exact_validation(lib):
     z = ctypes.c_void_p(16)
     assert lib.rtn_train_step(None, 1, 8, z, z, 1e-3, 0.9, 0.999, 1e-8, None, None) == RTN_EINVAL

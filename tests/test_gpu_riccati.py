@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from workload import config_workload, sample_horizons, offsets_from_horizons
-from oracle.riccati import riccati_batched, kkt_bruteforce
+from oracle.riccati import riccati_batched, kkt_bruteforce, lq_rollout_batched
 
 pytestmark = pytest.mark.gpu
 
@@ -100,3 +100,34 @@ def test_empty_and_single_node(torch):
     res = gpu_riccati(torch, A, B, Q, R, Q, off)
     K, kff, P = riccati_batched(off, A.astype(np.float64), B.astype(np.float64), Q, R, Q)
     assert rel_max(res["K"], K) < 1e-12
+
+
+def test_lq_rollout_matches_oracle_and_kkt(torch):
+    """rtn_lq_rollout on ragged instances vs the oracle's forward pass (same fp64 K, kff
+    from the GPU Riccati), and the rolled-out trajectory vs the dense KKT minimiser."""
+    import paper_2203_07747_amd as rtn
+    hz = sample_horizons(29, 1, 9, seed=6)
+    off = offsets_from_horizons(hz)
+    n, ni = int(off[-1]), len(hz)
+    A, B, rng = random_lq(n, 3)
+    c = rng.normal(size=(n, 13)) * 0.1
+    q = rng.normal(size=(n, 13)); r = rng.normal(size=(n, 4))
+    dx0 = rng.normal(size=(ni, 13))
+    Q = np.eye(13); R = 0.1 * np.eye(4); QN = np.eye(13)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    print(f"[gpu] lq_rollout n={n} n_inst={ni}", flush=True)
+    At, Bt, ct = dev(A), dev(B), dev(c)
+    ric = rtn.riccati(At, Bt, Q, R, QN, offsets=off, c=ct, q=dev(q), r=dev(r))
+    out = rtn.lq_rollout(At, Bt, ric["K"], ric["kff"], dev(dx0), offsets=off, c=ct)
+    torch.cuda.synchronize()
+    K, kff = ric["K"].cpu().numpy(), ric["kff"].cpu().numpy()
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    du, dx, dxN = lq_rollout_batched(off, A64, B64, K, kff, dx0, c)
+    assert rel_max(out["du"].cpu().numpy(), du) < 1e-12
+    assert rel_max(out["dx"].cpu().numpy(), dx) < 1e-12
+    assert rel_max(out["dxN"].cpu().numpy(), dxN) < 1e-12
+    for i in (0, ni // 2, ni - 1):
+        a, b = int(off[i]), int(off[i + 1])
+        du_ref, dx_ref = kkt_bruteforce(A64[a:b], B64[a:b], Q, R, QN, dx0[i], c[a:b], q[a:b], r[a:b])
+        np.testing.assert_allclose(out["du"].cpu().numpy()[a:b], du_ref, atol=1e-9)
+        np.testing.assert_allclose(out["dxN"].cpu().numpy()[i], dx_ref[-1], atol=1e-9)

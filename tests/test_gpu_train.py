@@ -132,11 +132,11 @@ def test_autograd_input_gradient_equals_linearizer_jacobian(torch):
     m.close()
 
 
-def test_trained_residual_beats_nominal_model(torch):
-    """Fit 14-4x512-6 (bf16, Adam lr 1e-3, batch 4096) to drag-simulator labels, then compare
-    the next-state error of the linearisation with the trained network against the nominal
-    model alone on held-out transitions."""
+@pytest.fixture(scope="module")
+def trained(torch):
+    """Fit 14-4x512-6 (bf16, Adam lr 1e-3, batch 4096) to drag-simulator labels."""
     import paper_2203_07747_amd as rtn
+    print("[gpu] training 14-4x512-6 bf16 on 400k simulator transitions", flush=True)
     dt = TRAIN["dt"]
     n_train = 400_000
     x, u = sample_nodes(n_train, seed=SEED_TRAIN)
@@ -158,7 +158,16 @@ def test_trained_residual_beats_nominal_model(torch):
                 first = float(loss.item())
         losses.append(float(loss.item()))
     print(f"  loss of the first batch {first:.4f}; last batch of each epoch:", [f"{v:.4f}" for v in losses])
-    # held-out transitions: the plant's next state vs the linearisation's phi-bar
+    yield m, first, losses
+    m.close()
+
+
+def test_trained_residual_beats_nominal_model(torch, trained):
+    """Next-state error of the linearisation with the trained network against the nominal
+    model alone on held-out transitions."""
+    import paper_2203_07747_amd as rtn
+    m, first, losses = trained
+    dt = TRAIN["dt"]
     xv, uv = sample_nodes(4096 * 20, seed=SEED_TRAIN + 7)
     xs, _ = make_transitions(xv, uv, dt, seed=SEED_TRAIN + 8)
     xt, ut = torch.from_numpy(xv).cuda(), torch.from_numpy(uv).cuda()
@@ -170,4 +179,21 @@ def test_trained_residual_beats_nominal_model(torch):
     print(f"  mean next-state [v, w] error: nominal {e_nom:.4e}  trained {e_lrn:.4e}  ratio {e_lrn / e_nom:.3f}")
     assert losses[-1] < 0.25 * first
     assert e_lrn < 0.5 * e_nom
-    m.close()
+
+
+def test_closed_loop_rollouts_trained_vs_nominal(torch, trained):
+    """4096 MPC instances (N = 20) tracking circles at 2-4 m/s in closed loop with the
+    drag plant, once with the trained residual and once with the nominal fallback: the
+    trained model's one-step predictions are closer to the plant and it tracks better."""
+    import paper_2203_07747_amd as rtn
+    from closed_loop import run
+    m, _, _ = trained
+    print("[gpu] closed loop nominal", flush=True)
+    nom = run(torch, rtn, None, "fp32")
+    print(f"  nominal: {nom}", flush=True)
+    print("[gpu] closed loop trained", flush=True)
+    lrn = run(torch, rtn, m, "bf16")
+    print(f"  trained: {lrn}", flush=True)
+    assert nom["finite"] and lrn["finite"]
+    assert lrn["pred_err"] < 0.5 * nom["pred_err"]
+    assert lrn["track_err"] < nom["track_err"]

@@ -16,7 +16,7 @@ from oracle.quadrotor import (nominal_f, nominal_jac, quat_mul, quat_conj, quat_
                               rotor_positions, ROTOR_SPIN, body_torque)
 from oracle.mlp import MLP, pack_input, residual_in_state, silu_prime
 from oracle.rk4 import (linearize_affine, linearize_exact, affine_phi, exact_phi, rk4_step)
-from oracle.riccati import riccati, riccati_batched, kkt_bruteforce
+from oracle.riccati import riccati, riccati_batched, kkt_bruteforce, lq_rollout, lq_rollout_batched
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DT = 0.05
@@ -380,3 +380,29 @@ def test_riccati_batched_ranges():
     K1, k1, _ = riccati(A[3:], B[3:], Q, R, QN, c[3:])
     np.testing.assert_array_equal(K, np.concatenate([K0, K1]))
     np.testing.assert_array_equal(kff, np.concatenate([k0, k1]))
+
+
+@pytest.mark.parametrize("N", [1, 3, 6])
+def test_lq_rollout_is_the_qp_minimiser(N):
+    """The forward pass of the Riccati solution reproduces the dense KKT primal solution
+    (every dx_k, du_k, and the terminal dx_N) for an arbitrary initial deviation."""
+    A, B, c, q, r, qN, Q, R, QN = _random_lq(N, seed=20 + N)
+    K, kff, _ = riccati(A, B, Q, R, QN, c, q, r, qN)
+    dx0 = np.random.default_rng(N).normal(size=13)
+    du_ref, dx_ref = kkt_bruteforce(A, B, Q, R, QN, dx0, c, q, r, qN)
+    du, dx = lq_rollout(A, B, K, kff, dx0, c)
+    np.testing.assert_allclose(du, du_ref, atol=1e-10)
+    np.testing.assert_allclose(dx, dx_ref, atol=1e-10)
+
+
+def test_lq_rollout_batched_ranges():
+    A, B, c, q, r, qN, Q, R, QN = _random_lq(7, seed=9)
+    off = np.array([0, 4, 7])
+    K, kff, _ = riccati_batched(off, A, B, Q, R, QN, c=c)
+    dx0 = np.random.default_rng(1).normal(size=(2, 13))
+    du, dx, dxN = lq_rollout_batched(off, A, B, K, kff, dx0, c)
+    for i, (a, b) in enumerate([(0, 4), (4, 7)]):
+        du_ref, dx_ref = kkt_bruteforce(A[a:b], B[a:b], Q, R, QN, dx0[i], c[a:b])
+        np.testing.assert_allclose(du[a:b], du_ref, atol=1e-10)
+        np.testing.assert_allclose(dx[a:b], dx_ref[:-1], atol=1e-10)
+        np.testing.assert_allclose(dxN[i], dx_ref[-1], atol=1e-10)

@@ -55,6 +55,17 @@ def measured_traffic(config_key: str, kernel_prefix: str):
     return None
 
 
+def tile_choice(rtn, prec, H, L, n):
+    """The autotuner's kept shapes for this workload: (forward variant, forward
+    workgroups, reverse variant, reverse workgroups) and the times it measured."""
+    got = rtn.tune_get(prec, H, L, n)
+    if got is None:
+        return None
+    ch, ms = got
+    return {"forward": {"variant": ch[0], "workgroups": ch[1], "tuning_ms": ms[0]},
+            "reverse": {"variant": ch[2], "workgroups": ch[3], "tuning_ms": ms[1]}}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -213,6 +224,7 @@ def main():
                      "traffic": measured_traffic(args.config, "mlp_reverse_chain"),
                      "algorithmic_flops_per_launch": n * f_rev, "avg_launch_ms": rev_ms},
         "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms},
+        "tile_choice": tile_choice(rtn, prec, H, L, n),
         "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,
         "host_wall_ms_per_step": wall_ms,
     }

@@ -237,6 +237,32 @@ rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch,
 rtn_status rtn_model_get_adam(rtn_model* model, float* m_host, float* v_host, int64_t* step);
 rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float* v_host, int64_t step);
 
+/* Tile autotuner of the network kernels.  For every (precision, width, depth,
+ * size class = floor(log2 n_nodes)) the first rtn_linearize call times each
+ * valid (tile variant, workgroup count) of the network forward and reverse
+ * kernels on its own inputs, synchronising its stream while it does so, and
+ * keeps the fastest; later calls, and the graphs captured from them, use the
+ * kept choice.  When the stream is being captured by the caller the default
+ * shapes are used and nothing is tuned.  RTN_TUNE=0 in the environment, or
+ * rtn_tune_mode(0), turns tuning off (default shapes unless an entry exists);
+ * RTN_TUNE_FILE=path loads a saved table before the first lookup and rewrites
+ * it after each new result.
+ *   choice[4] = {forward variant, forward workgroups, reverse variant, reverse
+ *               workgroups}: variant 0 is the default tile shape, 1 the
+ *               alternative shape (widths 512 and 1024); workgroups 0 = two per
+ *               compute unit (never more than there are row blocks).
+ *   ms[2]     nullable: forward and reverse kernel times measured when tuned.
+ * rtn_tune_get: RTN_EINVAL when the key has no entry.  rtn_tune_set: RTN_EINVAL
+ * when the choice names a shape that does not exist for the width.  The table
+ * is process-wide and guarded by a lock; save/load use a text file. */
+rtn_status rtn_tune_mode(int32_t on);
+rtn_status rtn_tune_get(int32_t prec, int32_t width, int32_t n_hidden, int32_t n_nodes,
+                        int32_t* choice, float* ms);
+rtn_status rtn_tune_set(int32_t prec, int32_t width, int32_t n_hidden, int32_t n_nodes,
+                        const int32_t* choice);
+rtn_status rtn_tune_save(const char* path);
+rtn_status rtn_tune_load(const char* path);
+
 /* Kernel timing (tracing).  When enabled, every kernel the library launches is
  * bracketed by a pair of HIP events recorded on the call's stream (a few
  * microseconds of overhead per launch; leave it off for production timing).

@@ -15,7 +15,8 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "linearize", "riccati", "version", "quad_struct", "PREC", "profile_enable", "profile_collect"]
+__all__ = ["Model", "linearize", "linearize_exact", "riccati", "lq_rollout", "version", "quad_struct", "PREC",
+           "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
 def version() -> str:
@@ -25,6 +26,34 @@ def version() -> str:
 def profile_enable(on: bool = True) -> None:
     """Bracket every library kernel with HIP events on its stream (see rtn_profile_enable)."""
     check(load().rtn_profile_enable(1 if on else 0), "rtn_profile_enable")
+
+
+def tune_mode(on: bool) -> None:
+    """Turn the first-use tile autotuner on or off (rtn_tune_mode)."""
+    check(load().rtn_tune_mode(1 if on else 0), "rtn_tune_mode")
+
+
+def tune_get(prec: str, width: int, n_hidden: int, n_nodes: int):
+    """The kept (forward variant, forward workgroups, reverse variant, reverse workgroups)
+    and the (forward, reverse) milliseconds measured when tuned, or None without an entry."""
+    ch = (ctypes.c_int32 * 4)()
+    ms = (ctypes.c_float * 2)()
+    if load().rtn_tune_get(PREC[prec], width, n_hidden, n_nodes, ch, ms) != 0:
+        return None
+    return tuple(ch), tuple(ms)
+
+
+def tune_set(prec: str, width: int, n_hidden: int, n_nodes: int, choice) -> None:
+    ch = (ctypes.c_int32 * 4)(*[int(c) for c in choice])
+    check(load().rtn_tune_set(PREC[prec], width, n_hidden, n_nodes, ch), "rtn_tune_set")
+
+
+def tune_save(path: str) -> None:
+    check(load().rtn_tune_save(path.encode()), "rtn_tune_save")
+
+
+def tune_load(path: str) -> None:
+    check(load().rtn_tune_load(path.encode()), "rtn_tune_load")
 
 
 def profile_collect() -> Dict[str, Dict[str, float]]:

@@ -53,6 +53,11 @@ SIGNATURES = {
                               c_void_p, c_void_p]),
     "rtn_lq_rollout": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "rtn_tune_mode": (c_int32, [c_int32]),
+    "rtn_tune_get": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "rtn_tune_set": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p]),
+    "rtn_tune_save": (c_int32, [ctypes.c_char_p]),
+    "rtn_tune_load": (c_int32, [ctypes.c_char_p]),
     "rtn_mlp_forward": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "rtn_mlp_backward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "rtn_model_zero_grad": (c_int32, [c_void_p, c_void_p]),

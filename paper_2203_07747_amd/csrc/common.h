@@ -104,4 +104,9 @@ template <int P> __device__ inline typename Mfma<P>::elem to_elem(float v, float
 template <> __device__ inline float to_elem<P_FP32>(float v, float) { return v; }
 template <> __device__ inline uint16_t to_elem<P_BF16>(float v, float) { return f32_to_bf16_rne(v); }
 
+// max(|v|) into *p (calibration); non-negative floats order like their bit patterns
+__device__ inline void atomic_amax(float* p, float v) {
+  atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
+}
+
 }  // namespace rtn

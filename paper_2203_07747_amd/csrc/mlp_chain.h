@@ -32,11 +32,34 @@ hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int tra
                        hipStream_t st);
 hipError_t launch_amax(const float* a, long n, float* out, hipStream_t st);
 hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st);
+// Launch configuration of a layer-chain kernel: tile variant (0 = default
+// shape, 1 = the alternative shape, widths 512 and 1024 only) and workgroup
+// count (0 = two per compute unit; never more than there are row blocks).
+struct ChainCfg {
+  int variant = 0;
+  int grid = 0;
+};
+constexpr int kChainVariants = 2;
+// Tile shape of a (precision, width, direction, variant): whether it exists,
+// waves per workgroup, rows per workgroup, and (when `occupancy` is set; this
+// asks the device) workgroups resident per compute unit, else 0.
+struct ChainGeom {
+  int valid, waves, rows, resident_per_cu;
+};
+hipError_t chain_geometry(int prec, int H, int rev, int variant, int occupancy, ChainGeom* g);
 hipError_t launch_mlp_forward(int prec, int H, const NetView& net, int n, const float* x, const float* u,
                               const float* zin, void* stash, float* y, float* amax, hipStream_t st,
-                              float* hsave = nullptr);
+                              float* hsave = nullptr, const ChainCfg& cfg = ChainCfg());
 hipError_t launch_mlp_reverse(int prec, int H, const NetView& net, int n, const void* stash, float* J, float* amax,
-                              hipStream_t st);
+                              hipStream_t st, const ChainCfg& cfg = ChainCfg());
+// per-precision instantiations (chain_fp32.hip, chain_bf16.hip, chain_fp8.hip)
+template <int P>
+hipError_t chain_forward(int H, const ChainCfg& cfg, const NetView& net, int n, const float* x, const float* u,
+                         const float* zin, void* stash, float* y, float* amax, float* hsave, hipStream_t st);
+template <int P>
+hipError_t chain_reverse(int H, const ChainCfg& cfg, const NetView& net, int n, const void* stash, float* J,
+                         float* amax, hipStream_t st);
+template <int P> hipError_t chain_geom(int H, int rev, int V, int occupancy, ChainGeom* g);
 int stash_elem_bytes(int prec);
 int num_cu();  // compute units of the current device (cached after the first call)
 hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st);

@@ -13,6 +13,7 @@
 #include "mlp_chain.h"
 #include "model.h"
 #include "profiler.h"
+#include "tune.h"
 
 using namespace rtn;
 
@@ -369,15 +370,29 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
   float* y = f_D ? f_D : m->tmp;
   float* J = J_D ? J_D : m->tmp + (size_t)n_nodes * kDout;
   const NetView v = m->view(prec);
+  // tile shapes and workgroup counts: the tuned choice for this size class,
+  // timed here on first use unless tuning is off or the stream is being captured
+  TuneChoice tc;
+  const TuneKey tk{prec, m->H, m->L, tune_size_class(n_nodes)};
+  if (!tune_lookup(tk, &tc) && tune_enabled()) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      HIP_TRY(tune_run(prec, m->H, v, n_nodes, x, u, m->stash, y, J, st, &tc));
+      tune_store(tk, tc);
+    }
+  }
   auto enqueue = [&](hipStream_t q) -> hipError_t {
     hipError_t e;
     {
       ProfScope ps("mlp_forward_chain", q);
-      if ((e = launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, q)) != hipSuccess) return e;
+      if ((e = launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, q, nullptr,
+                                  tc.fwd)) != hipSuccess)
+        return e;
     }
     {
       ProfScope ps("mlp_reverse_chain", q);
-      if ((e = launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, q)) != hipSuccess) return e;
+      if ((e = launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, q, tc.rev)) != hipSuccess) return e;
     }
     ProfScope ps("rk4_linearize", q);
     return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q);
@@ -402,7 +417,10 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
                             (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)J, (uint64_t)(uintptr_t)status,
                             (uint64_t)(uintptr_t)m->stash, ((uint64_t)qbits[0] << 32) | qbits[1],
                             ((uint64_t)qbits[2] << 32) | qbits[3], ((uint64_t)qbits[4] << 32) | qbits[5],
-                            ((uint64_t)qbits[6] << 32) | dtb, 0, 0};
+                            ((uint64_t)qbits[6] << 32) | dtb,
+                            (uint64_t)tc.fwd.variant | ((uint64_t)(uint32_t)tc.fwd.grid << 8) |
+                                ((uint64_t)tc.rev.variant << 40),
+                            (uint64_t)(uint32_t)tc.rev.grid};
   Model::GraphEntry* hit = nullptr;
   for (auto& g : m->graphs)
     if (!memcmp(g.key, key, sizeof key)) hit = &g;
@@ -513,6 +531,73 @@ extern "C" rtn_status rtn_lq_rollout(int32_t n_inst, const int32_t* offsets_host
   hipError_t e2 = hipFreeAsync(dev, st);
   if (e != hipSuccess) return hip_fail(e, "rtn_lq_rollout");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return RTN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+
+static rtn_status tune_key(int32_t prec, int32_t width, int32_t n_hidden, int32_t n_nodes, TuneKey* k) {
+  if (prec != RTN_FP32 && prec != RTN_BF16 && prec != RTN_FP8) return fail(RTN_EINVAL, "unknown precision %d", prec);
+  if (!width_supported(width)) return fail(RTN_EINVAL, "width %d has no kernels", width);
+  if (n_hidden < 1 || n_hidden > kMaxHidden) return fail(RTN_EINVAL, "n_hidden must be in [1, 16] (got %d)", n_hidden);
+  if (n_nodes < 1) return fail(RTN_EINVAL, "n_nodes must be positive (got %d)", n_nodes);
+  *k = TuneKey{prec, width, n_hidden, tune_size_class(n_nodes)};
+  return RTN_OK;
+}
+
+extern "C" rtn_status rtn_tune_mode(int32_t on) {
+  if (on != 0 && on != 1) return fail(RTN_EINVAL, "tune mode must be 0 or 1 (got %d)", on);
+  tune_set_enabled(on == 1);
+  return RTN_OK;
+}
+
+extern "C" rtn_status rtn_tune_get(int32_t prec, int32_t width, int32_t n_hidden, int32_t n_nodes, int32_t* choice,
+                                   float* ms) {
+  TuneKey k;
+  rtn_status s = tune_key(prec, width, n_hidden, n_nodes, &k);
+  if (s) return s;
+  if (!choice) return fail(RTN_EINVAL, "choice is NULL");
+  TuneChoice c;
+  if (!tune_lookup(k, &c)) return fail(RTN_EINVAL, "no tuned entry for this precision, width, depth and size");
+  choice[0] = c.fwd.variant;
+  choice[1] = c.fwd.grid;
+  choice[2] = c.rev.variant;
+  choice[3] = c.rev.grid;
+  if (ms) {
+    ms[0] = c.fwd_ms;
+    ms[1] = c.rev_ms;
+  }
+  return RTN_OK;
+}
+
+extern "C" rtn_status rtn_tune_set(int32_t prec, int32_t width, int32_t n_hidden, int32_t n_nodes,
+                                   const int32_t* choice) {
+  TuneKey k;
+  rtn_status s = tune_key(prec, width, n_hidden, n_nodes, &k);
+  if (s) return s;
+  if (!choice) return fail(RTN_EINVAL, "choice is NULL");
+  TuneChoice c;
+  c.fwd.variant = choice[0];
+  c.fwd.grid = choice[1];
+  c.rev.variant = choice[2];
+  c.rev.grid = choice[3];
+  if (!tune_choice_valid(prec, width, c))
+    return fail(RTN_EINVAL, "choice {%d, %d, %d, %d} names a tile shape or workgroup count that does not exist",
+                choice[0], choice[1], choice[2], choice[3]);
+  tune_store(k, c);
+  return RTN_OK;
+}
+
+extern "C" rtn_status rtn_tune_save(const char* path) {
+  if (!path) return fail(RTN_EINVAL, "path is NULL");
+  if (tune_save(path) != 0) return fail(RTN_EINVAL, "cannot write %s", path);
+  return RTN_OK;
+}
+
+extern "C" rtn_status rtn_tune_load(const char* path) {
+  if (!path) return fail(RTN_EINVAL, "path is NULL");
+  if (tune_load(path) < 0) return fail(RTN_EINVAL, "cannot read %s", path);
   return RTN_OK;
 }
 

@@ -267,3 +267,61 @@ def test_exact_linearisation_matches_oracle(torch, prec, tol):
     gap = rel(aff[1], ref[1]).max()
     print(f"  affine-vs-exact gap on A: {gap:.2e}")
     m.close()
+
+
+# --------------------------------------------------------------- tile autotuner
+# Every tile shape and workgroup count the autotuner can choose is a code path
+# of its own: each is forced here and checked against the oracle.
+
+@pytest.mark.parametrize("prec,H,L,tol", [("fp32", 512, 2, 1e-5), ("bf16", 512, 3, 1e-2), ("bf16", 1024, 2, 1e-2),
+                                          ("fp8", 512, 3, 5e-2), ("fp8", 1024, 2, 5e-2)])
+def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
+    import paper_2203_07747_amd as rtn
+    n = 733  # ragged in every tile height (32, 64, 96) for both directions
+    x, u = sample_nodes(n, seed=41)
+    Ws, bs = xavier_params(L, H, seed=42)
+    m = rtn.Model(Ws, bs)
+    if prec == "fp8":
+        xc, uc = sample_nodes(4096, seed=SEED_CALIB)
+        m.calibrate(torch.from_numpy(xc).cuda(), torch.from_numpy(uc).cuda())
+    ref = linearize_affine(x, u, MLP(Ws, bs), DT)
+    xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
+    base = None
+    try:
+        for choice in [(0, 0, 0, 0), (1, 0, 1, 0), (1, 1, 1, 1), (0, 3, 1, 7), (1, 5, 0, 2), (0, 10000, 0, 10000)]:
+            print(f"[gpu] tile choice {choice} prec={prec} H={H} L={L} n={n}", flush=True)
+            rtn.tune_set(prec, H, L, n, choice)
+            out = rtn.linearize(xt, ut, m, prec, DT)
+            torch.cuda.synchronize()
+            res = {k: v.cpu().numpy() for k, v in out.items()}
+            check_against(res, ref, tol)
+            if base is None:
+                base = res
+            else:  # against the default shape: same arithmetic up to the order of fp32 sums
+                assert np.median(rel(res["J_D"], base["J_D"])) < (1e-5 if prec == "fp32" else 2e-3)
+    finally:
+        rtn.tune_set(prec, H, L, n, (0, 0, 0, 0))
+        m.close()
+
+
+def test_autotuner_keeps_a_valid_choice_and_results_match(torch):
+    import paper_2203_07747_amd as rtn
+    cfg, off, x, u, Ws, bs = config_workload("c2")
+    x, u = np.tile(x, (300, 1)), np.tile(u, (300, 1))  # 6000 nodes: a size class no other test uses
+    n = x.shape[0]
+    m = rtn.Model(Ws, bs)
+    rtn.tune_mode(True)
+    assert rtn.tune_get("bf16", 512, 4, n) is None
+    print(f"[gpu] autotune n={n}", flush=True)
+    out = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), m, "bf16", DT)
+    torch.cuda.synchronize()
+    got = rtn.tune_get("bf16", 512, 4, n)
+    assert got is not None
+    choice, ms = got
+    print(f"  kept {choice}, forward {ms[0]:.3f} ms, reverse {ms[1]:.3f} ms", flush=True)
+    assert choice[0] in (0, 1) and choice[2] in (0, 1) and min(choice) >= 0 and ms[0] > 0 and ms[1] > 0
+    ref = linearize_affine(x[:20], u[:20], MLP(Ws, bs), DT)
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in range(0, n, 997):  # the tiled copies of the 20 nodes give the same outputs everywhere
+        check_against({kk: vv[k - k % 20:k - k % 20 + 20] for kk, vv in res.items()}, ref, 1e-2)
+    m.close()

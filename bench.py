@@ -56,14 +56,16 @@ def measured_traffic(config_key: str, kernel_prefix: str):
 
 
 def tile_choice(rtn, prec, H, L, n):
-    """The autotuner's kept shapes for this workload: (forward variant, forward
-    workgroups, reverse variant, reverse workgroups) and the times it measured."""
+    """The autotuner's kept path and shapes for this workload and the times it measured."""
     got = rtn.tune_get(prec, H, L, n)
     if got is None:
         return None
     ch, ms = got
-    return {"forward": {"variant": ch[0], "workgroups": ch[1], "tuning_ms": ms[0]},
-            "reverse": {"variant": ch[2], "workgroups": ch[3], "tuning_ms": ms[1]}}
+    if ch[0] == 1:
+        return {"path": "per-layer small-batch", "forward_tuning_ms": ms[0], "reverse_tuning_ms": ms[1]}
+    return {"path": "layer chain",
+            "forward": {"variant": ch[1], "workgroups": ch[2], "tuning_ms": ms[0]},
+            "reverse": {"variant": ch[3], "workgroups": ch[4], "tuning_ms": ms[1]}}
 
 
 def parse():
@@ -131,6 +133,16 @@ def extras(torch, rtn, lin_out, off, stream):
     Riccati solve of this workload's A_k, B_k, and one training step of the residual."""
     from workload import TRAIN, xavier_params as xp
     res = {}
+    # floor: replay of a captured graph holding one trivial kernel
+    cap = torch.cuda.Stream()
+    t1 = torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    gph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gph, stream=cap):
+        t1.add_(1.0)
+    torch.cuda.synchronize()
+    ms, _ = time_steps(torch, gph.replay, 200, 20, stream)
+    res["graph_launch_floor_us"] = ms * 1e3
     for key in ("c1", "c2"):
         cfg, o, x, u, Ws, bs = config_workload(key)
         m = rtn.Model(Ws, bs)
@@ -138,7 +150,15 @@ def extras(torch, rtn, lin_out, off, stream):
         out = {}
         f = lambda: rtn.linearize(xt, ut, m, "fp32", cfg.dt, offsets=o, out=out, stream=stream)
         ms, wall = time_steps(torch, f, 200, 20, stream)
-        res[f"latency_{key}"] = {"workload": cfg.name, "us_per_call": ms * 1e3, "host_us_per_call": wall * 1e3}
+        rtn.profile_enable(True)
+        for _ in range(20):
+            f()
+        torch.cuda.synchronize()
+        kern = rtn.profile_collect()
+        rtn.profile_enable(False)
+        res[f"latency_{key}"] = {"workload": cfg.name, "us_per_call": ms * 1e3, "host_us_per_call": wall * 1e3,
+                                 "tile_choice": tile_choice(rtn, "fp32", cfg.width, cfg.n_hidden, x.shape[0]),
+                                 "kernel_us_unbatched": {k: v["avg_ms"] * 1e3 for k, v in kern.items()}}
         m.close()
     Q = np.eye(13); R = 0.1 * np.eye(4)
     rout = {}

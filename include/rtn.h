@@ -237,24 +237,28 @@ rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch,
 rtn_status rtn_model_get_adam(rtn_model* model, float* m_host, float* v_host, int64_t* step);
 rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float* v_host, int64_t step);
 
-/* Tile autotuner of the network kernels.  For every (precision, width, depth,
+/* Autotuner of the network kernels.  For every (precision, width, depth,
  * size class = floor(log2 n_nodes)) the first rtn_linearize call times each
- * valid (tile variant, workgroup count) of the network forward and reverse
- * kernels on its own inputs, synchronising its stream while it does so, and
- * keeps the fastest; later calls, and the graphs captured from them, use the
- * kept choice.  When the stream is being captured by the caller the default
- * shapes are used and nothing is tuned.  RTN_TUNE=0 in the environment, or
- * rtn_tune_mode(0), turns tuning off (default shapes unless an entry exists);
- * RTN_TUNE_FILE=path loads a saved table before the first lookup and rewrites
- * it after each new result.
- *   choice[4] = {forward variant, forward workgroups, reverse variant, reverse
- *               workgroups}: variant 0 is the default tile shape, 1 the
- *               alternative shape (widths 512 and 1024); workgroups 0 = two per
- *               compute unit (never more than there are row blocks).
- *   ms[2]     nullable: forward and reverse kernel times measured when tuned.
+ * valid (tile variant, workgroup count) of the layer-chain forward and reverse
+ * kernels on its own inputs -- and, for fp32 batches of at most 4096 nodes, the
+ * small-batch path that launches one kernel per layer spread over many compute
+ * units -- synchronising its stream while it does so, and keeps the fastest;
+ * later calls, and the graphs captured from them, use the kept choice.  When
+ * the stream is being captured by the caller the default shapes are used and
+ * nothing is tuned.  RTN_TUNE=0 in the environment, or rtn_tune_mode(0), turns
+ * tuning off (default shapes unless an entry exists); RTN_TUNE_FILE=path loads
+ * a saved table before the first lookup and rewrites it after each new result.
+ *   choice[5] = {path, forward variant, forward workgroups, reverse variant,
+ *               reverse workgroups}: path 0 = layer-chain kernels, 1 = the
+ *               small-batch path (fp32 only; the other entries are then unused);
+ *               variant 0 is the default tile shape, 1 the alternative shape
+ *               (widths 512 and 1024); workgroups 0 = two per compute unit
+ *               (never more than there are row blocks).
+ *   ms[2]     nullable: forward and reverse times measured when tuned.
  * rtn_tune_get: RTN_EINVAL when the key has no entry.  rtn_tune_set: RTN_EINVAL
- * when the choice names a shape that does not exist for the width.  The table
- * is process-wide and guarded by a lock; save/load use a text file. */
+ * when the choice names a path or shape that does not exist for the precision
+ * and width.  The table is process-wide and guarded by a lock; save/load use a
+ * text file. */
 rtn_status rtn_tune_mode(int32_t on);
 rtn_status rtn_tune_get(int32_t prec, int32_t width, int32_t n_hidden, int32_t n_nodes,
                         int32_t* choice, float* ms);

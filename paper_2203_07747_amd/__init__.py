@@ -34,9 +34,10 @@ def tune_mode(on: bool) -> None:
 
 
 def tune_get(prec: str, width: int, n_hidden: int, n_nodes: int):
-    """The kept (forward variant, forward workgroups, reverse variant, reverse workgroups)
-    and the (forward, reverse) milliseconds measured when tuned, or None without an entry."""
-    ch = (ctypes.c_int32 * 4)()
+    """The kept (path, forward variant, forward workgroups, reverse variant, reverse
+    workgroups) and the (forward, reverse) milliseconds measured when tuned, or None
+    without an entry."""
+    ch = (ctypes.c_int32 * 5)()
     ms = (ctypes.c_float * 2)()
     if load().rtn_tune_get(PREC[prec], width, n_hidden, n_nodes, ch, ms) != 0:
         return None
@@ -44,7 +45,7 @@ def tune_get(prec: str, width: int, n_hidden: int, n_nodes: int):
 
 
 def tune_set(prec: str, width: int, n_hidden: int, n_nodes: int, choice) -> None:
-    ch = (ctypes.c_int32 * 4)(*[int(c) for c in choice])
+    ch = (ctypes.c_int32 * 5)(*[int(c) for c in choice])
     check(load().rtn_tune_set(PREC[prec], width, n_hidden, n_nodes, ch), "rtn_tune_set")
 
 

@@ -64,6 +64,19 @@ int stash_elem_bytes(int prec);
 int num_cu();  // compute units of the current device (cached after the first call)
 hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st);
 
+// Small-batch per-layer path (layer_lat.hip), fp32 master weights: W[l] is
+// W_{l+1} row-major [fan_out][fan_in], W[L] the output layer.
+struct LatNet {
+  int L, H, act;
+  const float* W[17];
+  const float* b[17];
+};
+// act: [2][n][H] ping-pong activations; sp: [L][n][H] activation derivatives;
+// g: [2][6n][H] ping-pong cotangents; y [n][6]; J [n][6][14].
+hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const float* u, float* act, float* sp, float* y,
+                              hipStream_t st);
+hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* g, float* J, hipStream_t st);
+
 struct QuadConst {
   float mass, Jx, Jy, Jz, arm, c_tau, g;
 };

@@ -55,6 +55,8 @@ struct Model {
   void drop_graphs();
   float* exact_ws = nullptr;  // exact linearisation: xs, kp, kacc [n][13]; dkp, dacc [n][17][13]
   int64_t exact_cap = 0;
+  float* lat_ws = nullptr;  // small-batch path: activations [2][n][H], cotangents [2][6n][H]
+  int64_t lat_cap = 0;
   std::vector<void*> allocs;
 
   ~Model();
@@ -64,6 +66,8 @@ struct Model {
   rtn_status repack(hipStream_t st);
   rtn_status ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st);
   NetView view(int prec) const;
+  LatNet lat_view() const;
+  rtn_status ensure_lat_workspace(int64_t n, hipStream_t st);
   rtn_status ensure_train_workspace(int64_t batch, hipStream_t st);
   int64_t layer_fan_in(int l) const;
   int64_t layer_fan_out(int l) const;

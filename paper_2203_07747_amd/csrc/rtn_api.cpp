@@ -180,6 +180,33 @@ rtn_status rtn::Model::repack(hipStream_t st) {
   return RTN_OK;
 }
 
+LatNet rtn::Model::lat_view() const {
+  LatNet v{};
+  v.L = L;
+  v.H = H;
+  v.act = desc.activation == RTN_ACT_SILU ? 0 : 1;
+  for (int l = 0; l <= L; ++l) {
+    v.W[l] = params + w_off[l];
+    v.b[l] = params + b_off[l];
+  }
+  return v;
+}
+
+rtn_status rtn::Model::ensure_lat_workspace(int64_t n, hipStream_t st) {
+  if (n <= lat_cap) return RTN_OK;
+  drop_graphs();
+  if (lat_ws) {
+    HIP_TRY(hipStreamSynchronize(st));
+    release(lat_ws);
+    lat_ws = nullptr;
+  }
+  lat_cap = 0;
+  rtn_status s = alloc((void**)&lat_ws, (size_t)n * H * (2 + 2 * 6) * 4);
+  if (s) return s;
+  lat_cap = n;
+  return RTN_OK;
+}
+
 rtn_status rtn::Model::ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st) {
   (void)nrow_train;
   const size_t need = (size_t)L * n * H * 4;  // fp32 stash is the largest
@@ -374,16 +401,36 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
   // timed here on first use unless tuning is off or the stream is being captured
   TuneChoice tc;
   const TuneKey tk{prec, m->H, m->L, tune_size_class(n_nodes)};
+  const LatNet lv = m->lat_view();
+  const bool lat_ok = prec == RTN_FP32 && n_nodes <= kLatMaxNodes;
+  if (lat_ok && (s = m->ensure_lat_workspace(n_nodes, st))) return s;
+  float* lat_act = m->lat_ws;
+  float* lat_g = lat_ok ? m->lat_ws + (size_t)2 * n_nodes * m->H : nullptr;
   if (!tune_lookup(tk, &tc) && tune_enabled()) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cs));
     if (cs == hipStreamCaptureStatusNone) {
-      HIP_TRY(tune_run(prec, m->H, v, n_nodes, x, u, m->stash, y, J, st, &tc));
+      HIP_TRY(tune_run(prec, m->H, v, n_nodes, x, u, m->stash, y, J, lat_ok ? &lv : nullptr, lat_act, lat_g, st,
+                       &tc));
       tune_store(tk, tc);
     }
   }
+  if (tc.path == 1 && !lat_ok) tc = TuneChoice();  // an entry of this size class made for fewer nodes
   auto enqueue = [&](hipStream_t q) -> hipError_t {
     hipError_t e;
+    if (tc.path == 1) {
+      {
+        ProfScope ps("lat_forward", q);
+        if ((e = launch_lat_forward(lv, n_nodes, x, u, lat_act, static_cast<float*>(m->stash), y, q)) != hipSuccess)
+          return e;
+      }
+      {
+        ProfScope ps("lat_reverse", q);
+        if ((e = launch_lat_reverse(lv, n_nodes, static_cast<float*>(m->stash), lat_g, J, q)) != hipSuccess) return e;
+      }
+      ProfScope ps("rk4_linearize", q);
+      return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q);
+    }
     {
       ProfScope ps("mlp_forward_chain", q);
       if ((e = launch_mlp_forward(prec, m->H, v, n_nodes, x, u, nullptr, m->stash, y, nullptr, q, nullptr,
@@ -419,7 +466,7 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
                             ((uint64_t)qbits[2] << 32) | qbits[3], ((uint64_t)qbits[4] << 32) | qbits[5],
                             ((uint64_t)qbits[6] << 32) | dtb,
                             (uint64_t)tc.fwd.variant | ((uint64_t)(uint32_t)tc.fwd.grid << 8) |
-                                ((uint64_t)tc.rev.variant << 40),
+                                ((uint64_t)tc.rev.variant << 40) | ((uint64_t)tc.path << 48),
                             (uint64_t)(uint32_t)tc.rev.grid};
   Model::GraphEntry* hit = nullptr;
   for (auto& g : m->graphs)
@@ -560,10 +607,11 @@ extern "C" rtn_status rtn_tune_get(int32_t prec, int32_t width, int32_t n_hidden
   if (!choice) return fail(RTN_EINVAL, "choice is NULL");
   TuneChoice c;
   if (!tune_lookup(k, &c)) return fail(RTN_EINVAL, "no tuned entry for this precision, width, depth and size");
-  choice[0] = c.fwd.variant;
-  choice[1] = c.fwd.grid;
-  choice[2] = c.rev.variant;
-  choice[3] = c.rev.grid;
+  choice[0] = c.path;
+  choice[1] = c.fwd.variant;
+  choice[2] = c.fwd.grid;
+  choice[3] = c.rev.variant;
+  choice[4] = c.rev.grid;
   if (ms) {
     ms[0] = c.fwd_ms;
     ms[1] = c.rev_ms;
@@ -578,13 +626,14 @@ extern "C" rtn_status rtn_tune_set(int32_t prec, int32_t width, int32_t n_hidden
   if (s) return s;
   if (!choice) return fail(RTN_EINVAL, "choice is NULL");
   TuneChoice c;
-  c.fwd.variant = choice[0];
-  c.fwd.grid = choice[1];
-  c.rev.variant = choice[2];
-  c.rev.grid = choice[3];
+  c.path = choice[0];
+  c.fwd.variant = choice[1];
+  c.fwd.grid = choice[2];
+  c.rev.variant = choice[3];
+  c.rev.grid = choice[4];
   if (!tune_choice_valid(prec, width, c))
-    return fail(RTN_EINVAL, "choice {%d, %d, %d, %d} names a tile shape or workgroup count that does not exist",
-                choice[0], choice[1], choice[2], choice[3]);
+    return fail(RTN_EINVAL, "choice {%d, %d, %d, %d, %d} names a path, tile shape or workgroup count that does not exist",
+                choice[0], choice[1], choice[2], choice[3], choice[4]);
   tune_store(k, c);
   return RTN_OK;
 }

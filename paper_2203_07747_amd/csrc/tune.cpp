@@ -59,8 +59,8 @@ int load_locked(const char* path) {
     TuneKey k;
     TuneChoice c;
     if (line[0] == '#') continue;
-    if (sscanf(line, "%d %d %d %d %d %d %d %d %f %f", &k.prec, &k.H, &k.L, &k.size_class, &c.fwd.variant,
-               &c.fwd.grid, &c.rev.variant, &c.rev.grid, &c.fwd_ms, &c.rev_ms) == 10 &&
+    if (sscanf(line, "%d %d %d %d %d %d %d %d %d %f %f", &k.prec, &k.H, &k.L, &k.size_class, &c.path,
+               &c.fwd.variant, &c.fwd.grid, &c.rev.variant, &c.rev.grid, &c.fwd_ms, &c.rev_ms) == 11 &&
         tune_choice_valid(k.prec, k.H, c)) {
       store_locked(k, c);
       ++count;
@@ -73,10 +73,10 @@ int load_locked(const char* path) {
 int save_locked(const char* path) {
   FILE* f = fopen(path, "w");
   if (!f) return -1;
-  fprintf(f, "# prec width n_hidden size_class fwd_variant fwd_grid rev_variant rev_grid fwd_ms rev_ms\n");
+  fprintf(f, "# prec width n_hidden size_class path fwd_variant fwd_grid rev_variant rev_grid fwd_ms rev_ms\n");
   for (const auto& e : g_table)
-    fprintf(f, "%d %d %d %d %d %d %d %d %.6f %.6f\n", e.k.prec, e.k.H, e.k.L, e.k.size_class, e.c.fwd.variant,
-            e.c.fwd.grid, e.c.rev.variant, e.c.rev.grid, e.c.fwd_ms, e.c.rev_ms);
+    fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f %.6f\n", e.k.prec, e.k.H, e.k.L, e.k.size_class, e.c.path,
+            e.c.fwd.variant, e.c.fwd.grid, e.c.rev.variant, e.c.rev.grid, e.c.fwd_ms, e.c.rev_ms);
   return fclose(f) == 0 ? 0 : -1;
 }
 
@@ -141,6 +141,8 @@ void tune_store(const TuneKey& k, const TuneChoice& c) {
 
 bool tune_choice_valid(int prec, int H, const TuneChoice& c) {
   if (prec < P_FP32 || prec > P_FP8) return false;
+  if (c.path != 0 && c.path != 1) return false;
+  if (c.path == 1 && prec != P_FP32) return false;
   if (c.fwd.grid < 0 || c.rev.grid < 0) return false;
   if (c.fwd.variant < 0 || c.fwd.variant >= kChainVariants) return false;
   if (c.rev.variant < 0 || c.rev.variant >= kChainVariants) return false;
@@ -164,7 +166,7 @@ int tune_load(const char* path) {
 }
 
 hipError_t tune_run(int prec, int H, const NetView& net, int n, const float* x, const float* u, void* stash, float* y,
-                    float* J, hipStream_t st, TuneChoice* out) {
+                    float* J, const LatNet* lat, float* lat_act, float* lat_g, hipStream_t st, TuneChoice* out) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
@@ -225,11 +227,24 @@ hipError_t tune_run(int prec, int H, const NetView& net, int n, const float* x, 
       }
     }
   }
+  best.fwd_ms = best_f;
+  best.rev_ms = best_r;
+  // the small-batch per-layer path against the best chain pair
+  if (err == hipSuccess && lat && prec == P_FP32 && n <= kLatMaxNodes) {
+    float lf = 0.f, lr = 0.f;
+    float* sp = static_cast<float*>(stash);
+    err = time_launch([&] { return launch_lat_forward(*lat, n, x, u, lat_act, sp, y, st); }, &lf);
+    if (err == hipSuccess) err = time_launch([&] { return launch_lat_reverse(*lat, n, sp, lat_g, J, st); }, &lr);
+    if (err == hipSuccess && lf + lr < best_f + best_r) {
+      best = TuneChoice();
+      best.path = 1;
+      best.fwd_ms = lf;
+      best.rev_ms = lr;
+    }
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (err != hipSuccess) return err;
-  best.fwd_ms = best_f;
-  best.rev_ms = best_r;
   *out = best;
   return hipSuccess;
 }

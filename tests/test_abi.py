@@ -125,28 +125,31 @@ def test_lq_rollout_validation(lib):
 
 def test_tune_table_host_logic(lib, tmp_path):
     """The autotuner's table: validation of keys and choices, set/get, save/load (no GPU)."""
-    ch = (ctypes.c_int32 * 4)
+    ch = (ctypes.c_int32 * 5)
     ms = (ctypes.c_float * 2)()
     out = ch()
     assert lib.rtn_tune_mode(2) == RTN_EINVAL
-    assert lib.rtn_tune_get(7, 512, 4, 100, out, None) == RTN_EINVAL       # precision
-    assert lib.rtn_tune_get(1, 500, 4, 100, out, None) == RTN_EINVAL       # width without kernels
-    assert lib.rtn_tune_get(1, 512, 0, 100, out, None) == RTN_EINVAL       # depth
-    assert lib.rtn_tune_get(1, 512, 4, 0, out, None) == RTN_EINVAL        # size
-    assert lib.rtn_tune_set(1, 64, 2, 100, ch(1, 0, 0, 0)) == RTN_EINVAL   # no alternative shape at width 64
-    assert lib.rtn_tune_set(0, 1024, 2, 100, ch(0, 0, 1, 0)) == RTN_EINVAL  # fp32 width 1024 has none either
-    assert lib.rtn_tune_set(1, 512, 4, 100, ch(0, -1, 0, 0)) == RTN_EINVAL  # negative workgroups
-    assert lib.rtn_tune_set(1, 512, 4, 100, ch(1, 300, 0, 512)) == RTN_OK
-    assert lib.rtn_tune_get(1, 512, 4, 127, out, ms) == RTN_OK             # same size class (64..127)
-    assert tuple(out) == (1, 300, 0, 512)
-    assert lib.rtn_tune_get(1, 512, 4, 128, out, None) == RTN_EINVAL      # next size class
+    assert lib.rtn_tune_get(7, 512, 4, 100, out, None) == RTN_EINVAL          # precision
+    assert lib.rtn_tune_get(1, 500, 4, 100, out, None) == RTN_EINVAL          # width without kernels
+    assert lib.rtn_tune_get(1, 512, 0, 100, out, None) == RTN_EINVAL          # depth
+    assert lib.rtn_tune_get(1, 512, 4, 0, out, None) == RTN_EINVAL           # size
+    assert lib.rtn_tune_set(1, 64, 2, 100, ch(0, 1, 0, 0, 0)) == RTN_EINVAL   # no alternative shape at width 64
+    assert lib.rtn_tune_set(0, 1024, 2, 100, ch(0, 0, 0, 1, 0)) == RTN_EINVAL  # fp32 width 1024 has none either
+    assert lib.rtn_tune_set(1, 512, 4, 100, ch(0, 0, -1, 0, 0)) == RTN_EINVAL  # negative workgroups
+    assert lib.rtn_tune_set(1, 512, 4, 100, ch(1, 0, 0, 0, 0)) == RTN_EINVAL   # small-batch path is fp32 only
+    assert lib.rtn_tune_set(0, 512, 4, 100, ch(2, 0, 0, 0, 0)) == RTN_EINVAL   # no such path
+    assert lib.rtn_tune_set(0, 512, 4, 100, ch(1, 0, 0, 0, 0)) == RTN_OK
+    assert lib.rtn_tune_set(1, 512, 4, 100, ch(0, 1, 300, 0, 512)) == RTN_OK
+    assert lib.rtn_tune_get(1, 512, 4, 127, out, ms) == RTN_OK                # same size class (64..127)
+    assert tuple(out) == (0, 1, 300, 0, 512)
+    assert lib.rtn_tune_get(1, 512, 4, 128, out, None) == RTN_EINVAL         # next size class
     path = str(tmp_path / "tune.txt")
     assert lib.rtn_tune_save(path.encode()) == RTN_OK
     text = open(path).read()
-    assert "1 512 4 6 1 300 0 512" in text
-    assert lib.rtn_tune_set(1, 512, 4, 100, ch(0, 0, 1, 0)) == RTN_OK
+    assert "1 512 4 6 0 1 300 0 512" in text and "0 512 4 6 1 0 0 0 0" in text
+    assert lib.rtn_tune_set(1, 512, 4, 100, ch(0, 0, 0, 1, 0)) == RTN_OK
     assert lib.rtn_tune_load(path.encode()) == RTN_OK
-    assert lib.rtn_tune_get(1, 512, 4, 100, out, None) == RTN_OK and tuple(out) == (1, 300, 0, 512)
+    assert lib.rtn_tune_get(1, 512, 4, 100, out, None) == RTN_OK and tuple(out) == (0, 1, 300, 0, 512)
     assert lib.rtn_tune_load(str(tmp_path / "missing.txt").encode()) == RTN_EINVAL
 
 

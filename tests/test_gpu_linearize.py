@@ -288,7 +288,8 @@ def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
     xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
     base = None
     try:
-        for choice in [(0, 0, 0, 0), (1, 0, 1, 0), (1, 1, 1, 1), (0, 3, 1, 7), (1, 5, 0, 2), (0, 10000, 0, 10000)]:
+        for choice in [(0, 0, 0, 0, 0), (0, 1, 0, 1, 0), (0, 1, 1, 1, 1), (0, 0, 3, 1, 7), (0, 1, 5, 0, 2),
+                       (0, 0, 10000, 0, 10000)]:
             print(f"[gpu] tile choice {choice} prec={prec} H={H} L={L} n={n}", flush=True)
             rtn.tune_set(prec, H, L, n, choice)
             out = rtn.linearize(xt, ut, m, prec, DT)
@@ -300,7 +301,7 @@ def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
             else:  # against the default shape: same arithmetic up to the order of fp32 sums
                 assert np.median(rel(res["J_D"], base["J_D"])) < (1e-5 if prec == "fp32" else 2e-3)
     finally:
-        rtn.tune_set(prec, H, L, n, (0, 0, 0, 0))
+        rtn.tune_set(prec, H, L, n, (0, 0, 0, 0, 0))
         m.close()
 
 
@@ -319,9 +320,31 @@ def test_autotuner_keeps_a_valid_choice_and_results_match(torch):
     assert got is not None
     choice, ms = got
     print(f"  kept {choice}, forward {ms[0]:.3f} ms, reverse {ms[1]:.3f} ms", flush=True)
-    assert choice[0] in (0, 1) and choice[2] in (0, 1) and min(choice) >= 0 and ms[0] > 0 and ms[1] > 0
+    assert choice[0] == 0 and choice[1] in (0, 1) and choice[3] in (0, 1) and min(choice) >= 0
+    assert ms[0] > 0 and ms[1] > 0
     ref = linearize_affine(x[:20], u[:20], MLP(Ws, bs), DT)
     res = {k: v.cpu().numpy() for k, v in out.items()}
     for k in range(0, n, 997):  # the tiled copies of the 20 nodes give the same outputs everywhere
         check_against({kk: vv[k - k % 20:k - k % 20 + 20] for kk, vv in res.items()}, ref, 1e-2)
     m.close()
+
+
+@pytest.mark.parametrize("H,L,n", [(64, 2, 10), (64, 1, 7), (512, 4, 20), (256, 3, 45), (1024, 2, 33), (128, 5, 300)])
+def test_small_batch_path_matches_oracle(torch, H, L, n):
+    """The per-layer small-batch path (fp32), forced through the tuning table."""
+    import paper_2203_07747_amd as rtn
+    x, u = sample_nodes(n, seed=51)
+    Ws, bs = xavier_params(L, H, seed=52)
+    bs = [np.random.default_rng(53).normal(size=b.shape).astype(np.float32) * 0.1 for b in bs]
+    m = rtn.Model(Ws, bs)
+    try:
+        rtn.tune_set("fp32", H, L, n, (1, 0, 0, 0, 0))
+        print(f"[gpu] small-batch path H={H} L={L} n={n}", flush=True)
+        out = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), m, "fp32", DT)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        errs = check_against(res, linearize_affine(x, u, MLP(Ws, bs), DT), 1e-5)
+        assert errs["f_D"] < 1e-5 and errs["J_D"] < 1e-5
+    finally:
+        rtn.tune_set("fp32", H, L, n, (0, 0, 0, 0, 0))
+        m.close()

@@ -46,20 +46,37 @@ template <int P, int H, bool REV> struct ChainShapeDefault {
                                        : (H <= 256 ? 128 : 64);
 };
 
-// Variant V = 0 is the default shape above; V = 1 is the alternative the
+// Variant V = 0 is the default shape above; V = 1 and 2 are alternatives the
 // autotuner may pick instead (widths 512 and 1024 only):
-//   default with one wave per SIMD       -> two waves per SIMD, 64 rows
-//   bf16/fp8 width 512, two waves per SIMD -> one wave per SIMD, 96 rows
-//   otherwise                             -> the same waves, half the rows
+//   V = 1: default with one wave per SIMD       -> two waves per SIMD, 64 rows;
+//          bf16/fp8 width 512, two waves per SIMD -> one wave per SIMD, 96 rows;
+//          otherwise                             -> the same waves, half the rows
+//   V = 2: one wave per SIMD with half the register file and at most 80 KB of
+//          LDS (64 rows, else 32), so that two workgroups share a compute unit
+//          and one's epilogue overlaps the other's matrix work.
+// OCC is the number of waves per SIMD the register budget is sized for.
 template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
   using D = ChainShapeDefault<P, H, REV>;
   static constexpr bool ALT_ONE = !D::ONE_PER_SIMD && H == 512 && P != P_FP32;
-  static constexpr int NW = V == 0 ? D::NW : (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW));
-  static constexpr int R = V == 0 ? D::R : (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2));
-  static constexpr bool VALID = V == 0 || (H >= 512 && R >= 32);
+  static constexpr int ESZ = P == P_FP32 ? 4 : (P == P_BF16 ? 2 : 1);
+  static constexpr int SPE = P == P_FP32 ? 4 : 2;
+  // operand rows + (reverse) staged derivatives of a 64-row block within 80 KB
+  static constexpr bool FITS64 = 64 * H * ESZ + (REV ? 12 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
+                                 (H / 32 / 4) * 2 * 16 <= 128;
+  static constexpr int R2 = FITS64 ? 64 : 32;
+  static constexpr int NW = V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : 4;
+  static constexpr int R = V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : R2;
+  static constexpr int OCC = V == 2 ? 2 : (NW <= 4 ? 1 : 2);
+  static constexpr bool VALID =
+      V == 0 || (V == 1 && H >= 512 && R >= 32) ||
+      (V == 2 && H >= 512 && R * H * ESZ + (REV ? 7 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
+       (H / 32 / 4) * (R / 32) * 16 <= 128);
 };
 
-template <int P, int H, int R, int NW> struct Chain {
+// OCC: waves per SIMD the kernel is built for (1: the whole register file and,
+// with 4 waves, the whole LDS; 2: half of each when the workgroup has 4 waves).
+template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain {
+  static constexpr int kOcc = OCC;
   using M = Mfma<P>;
   using elem = typename M::elem;
   using frag = typename M::frag;
@@ -82,11 +99,13 @@ template <int P, int H, int R, int NW> struct Chain {
   static constexpr int SP_CHUNKS_PER_THREAD = (SP_NODES * SP_ROW_CHUNKS + NW * kWave - 1) / (NW * kWave);
   // output weights stay resident in LDS for the whole kernel when they fit
   static constexpr int WOS = H + 4;  // LDS row stride (floats): 16-byte pad against bank conflicts
-  static constexpr bool WO_IN_LDS = LDS_BYTES + SP_BYTES + kDout * WOS * 4 <= 160 * 1024;
+  static constexpr int LDS_CAP = 160 * 1024 * NW / (4 * OCC);
+  static constexpr bool WO_IN_LDS = LDS_BYTES + SP_BYTES + kDout * WOS * 4 <= LDS_CAP;
   static constexpr int WO_BYTES = WO_IN_LDS ? kDout * WOS * 4 : 0;
   static constexpr int REV_LDS_BYTES = LDS_BYTES + SP_BYTES + WO_BYTES;
   static_assert(MT % NW == 0, "width must split evenly over the waves");
-  static_assert(MTW * RT * 16 <= (NW <= 4 ? 192 : 128), "accumulator budget");
+  static_assert(MTW * RT * 16 <= (OCC == 1 ? 192 : 128), "accumulator budget");
+  static_assert(REV_LDS_BYTES <= LDS_CAP || LDS_BYTES <= LDS_CAP, "LDS budget");
 
   // LDS element index of (row tile, K-step, lane, slot-in-step) for an operand with KS K-steps.
   __device__ static inline int lidx(int rt, int s, int lane, int KS) { return ((rt * KS + s) * kWave + lane) * E; }
@@ -118,7 +137,7 @@ template <int P, int H, int R, int NW> struct Chain {
                                          int mt0, int s0, int rot, const BSrc& bsrc, int lane) {
     // ring depth: up to 4 steps, at most 128 (two waves per SIMD) or 256 (one wave
     // per SIMD) bytes of weight fragments per lane
-    constexpr int PD0 = (RING ? RING : (NW <= 4 ? 256 : 128)) / (NMT * (int)sizeof(frag));
+    constexpr int PD0 = (RING ? RING : (OCC == 1 ? 256 : 128)) / (NMT * (int)sizeof(frag));
     constexpr int PD1 = PD0 < 1 ? 1 : (PD0 > 4 ? 4 : PD0);
     constexpr int PD = NSTEPS < PD1 ? NSTEPS : PD1;
     static_assert(NSTEPS % PD == 0, "K-steps must be a multiple of the prefetch depth");
@@ -326,12 +345,13 @@ __device__ inline float from_stash(uint16_t v) { return bf16_to_f32(v); }
 // ---------------------------------------------------------------------------
 // Forward chain: z_0 -> h_1..h_L (stash act'), y.
 template <int P, int H, int V>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, false, V>::NW * kWave)))
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, false, V>::NW * kWave),
+                               amdgpu_waves_per_eu(ChainShape<P, H, false, V>::OCC)))
 mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* __restrict__ u,
                   const float* __restrict__ zin, typename StashT<P>::type* __restrict__ stash,
                   float* __restrict__ y, float* __restrict__ amax, float* __restrict__ hsave) {
   constexpr int NW = ChainShape<P, H, false, V>::NW, R = ChainShape<P, H, false, V>::R;
-  using C = Chain<P, H, R, NW>;
+  using C = Chain<P, H, R, NW, ChainShape<P, H, false, V>::OCC>;
   using elem = typename C::elem;
   using frag = typename C::frag;
   using S = typename StashT<P>::type;
@@ -378,7 +398,7 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
         C::template gemm<C::MTW, C::KS_1>(acc, reinterpret_cast<const frag*>(net.fw[0]), C::MT, C::KS_1, wave * C::MTW,
                                           0, blk, lds, lane);
       else
-        C::template gemm<C::MTW, C::KS_H, (NW > 4 ? 64 : 0)>(acc, reinterpret_cast<const frag*>(net.fw[layer]), C::MT,
+        C::template gemm<C::MTW, C::KS_H, (C::kOcc > 1 ? 64 : 0)>(acc, reinterpret_cast<const frag*>(net.fw[layer]), C::MT,
                                                               C::KS_H, wave * C::MTW, 0, blk, lds, lane);
       __syncthreads();
       const float scale = P == P_FP8 ? dq[layer] * net.ascale[layer] : 1.f;
@@ -462,11 +482,12 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
 // the matrix work) and parked in LDS when the loop ends; the next block's
 // first-layer rows are fetched during the current block's last K-loop.
 template <int P, int H, int V>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, true, V>::NW * kWave)))
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, true, V>::NW * kWave),
+                               amdgpu_waves_per_eu(ChainShape<P, H, true, V>::OCC)))
 mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict__ stash,
                   float* __restrict__ J, float* __restrict__ amax) {
   constexpr int NW = ChainShape<P, H, true, V>::NW, R = ChainShape<P, H, true, V>::R;
-  using C = Chain<P, H, R, NW>;
+  using C = Chain<P, H, R, NW, ChainShape<P, H, true, V>::OCC>;
   using elem = typename C::elem;
   using frag = typename C::frag;
   using S = typename StashT<P>::type;
@@ -570,7 +591,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
       // with one wave per SIMD there are registers to read all of this wave's
       // activation-derivative runs (16 stash values = 32 or 64 bytes each, kept
       // packed) before their first use
-      constexpr bool PRE = NW <= 4;
+      constexpr bool PRE = C::kOcc == 1;
       constexpr int PI = PRE ? C::MTW : 1, PR = PRE ? C::RT : 1;
       constexpr int RUN_CH = 16 * (int)sizeof(S) / 16;  // 16-byte chunks per run
       i32x4 spraw[PI][PR][RUN_CH];
@@ -706,8 +727,10 @@ template <int P, int H, int V> hipError_t chain_geom_v(int rev, int occupancy, C
     case 256 * 4: return FN<P, 256, 0>(__VA_ARGS__);           \
     case 512 * 4: return FN<P, 512, 0>(__VA_ARGS__);           \
     case 512 * 4 + 1: return FN<P, 512, 1>(__VA_ARGS__);       \
+    case 512 * 4 + 2: return FN<P, 512, 2>(__VA_ARGS__);       \
     case 1024 * 4: return FN<P, 1024, 0>(__VA_ARGS__);         \
     case 1024 * 4 + 1: return FN<P, 1024, 1>(__VA_ARGS__);     \
+    case 1024 * 4 + 2: return FN<P, 1024, 2>(__VA_ARGS__);     \
     default: return hipErrorInvalidValue;                      \
   }
 

@@ -24,8 +24,17 @@ constexpr int kNodesPerBlock = 16;
 constexpr int kNodeStride = 108;  // x 13 | u 4 | y 6 | J 84 | pad 1
 
 
+// Reciprocals of the mass and the principal inertias, formed once per thread:
+// the model divides by these constants many times per stage.
+struct QuadInv {
+  float m, Jx, Jy, Jz;
+};
+__device__ inline QuadInv quad_inv(const QuadConst& P) {
+  return QuadInv{1.f / P.mass, 1.f / P.Jx, 1.f / P.Jy, 1.f / P.Jz};
+}
+
 // f_F(x, u) with T = sum u, tau from the X-frame mixer; closed form of eq. (6).
-__device__ inline void nominal_rhs(const float* x, const float* u, const QuadConst& P, float* f) {
+__device__ inline void nominal_rhs(const float* x, const float* u, const QuadConst& P, const QuadInv& I, float* f) {
   const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   const float wx = x[10], wy = x[11], wz = x[12];
   const float T = u[0] + u[1] + u[2] + u[3];
@@ -37,21 +46,21 @@ __device__ inline void nominal_rhs(const float* x, const float* u, const QuadCon
   f[4] = 0.5f * (qw * wx + qy * wz - qz * wy);
   f[5] = 0.5f * (qw * wy - qx * wz + qz * wx);
   f[6] = 0.5f * (qw * wz + qx * wy - qy * wx);
-  const float Tm = T / P.mass;
+  const float Tm = T * I.m;
   f[7] = Tm * 2.f * (qx * qz + qw * qy);
   f[8] = Tm * 2.f * (qy * qz - qw * qx);
   f[9] = Tm * (qw * qw - qx * qx - qy * qy + qz * qz) - P.g;
   const float tx = h * (-u[0] - u[1] + u[2] + u[3]);
   const float ty = h * (-u[0] + u[1] + u[2] - u[3]);
   const float tz = P.c_tau * (-u[0] + u[1] - u[2] + u[3]);
-  f[10] = (tx - (P.Jz - P.Jy) * wy * wz) / P.Jx;
-  f[11] = (ty - (P.Jx - P.Jz) * wz * wx) / P.Jy;
-  f[12] = (tz - (P.Jy - P.Jx) * wx * wy) / P.Jz;
+  f[10] = (tx - (P.Jz - P.Jy) * wy * wz) * I.Jx;
+  f[11] = (ty - (P.Jx - P.Jz) * wz * wx) * I.Jy;
+  f[12] = (tz - (P.Jy - P.Jx) * wx * wy) * I.Jz;
 }
 
 // (df_F/dx) d at x (directional derivative along the state tangent d).
-__device__ inline void nominal_tangent(const float* x, const float* u, const QuadConst& P, const float* d,
-                                       float* df) {
+__device__ inline void nominal_tangent(const float* x, const float* u, const QuadConst& P, const QuadInv& I,
+                                       const float* d, float* df) {
   const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   const float wx = x[10], wy = x[11], wz = x[12];
   const float dqw = d[3], dqx = d[4], dqy = d[5], dqz = d[6];
@@ -65,13 +74,13 @@ __device__ inline void nominal_tangent(const float* x, const float* u, const Qua
   df[4] = 0.5f * (dqw * wx + dqy * wz - dqz * wy + qw * dwx + qy * dwz - qz * dwy);
   df[5] = 0.5f * (dqw * wy - dqx * wz + dqz * wx + qw * dwy - qx * dwz + qz * dwx);
   df[6] = 0.5f * (dqw * wz + dqx * wy - dqy * wx + qw * dwz + qx * dwy - qy * dwx);
-  const float Tm = T / P.mass;
+  const float Tm = T * I.m;
   df[7] = Tm * 2.f * (dqx * qz + qx * dqz + dqw * qy + qw * dqy);
   df[8] = Tm * 2.f * (dqy * qz + qy * dqz - dqw * qx - qw * dqx);
   df[9] = Tm * 2.f * (qw * dqw - qx * dqx - qy * dqy + qz * dqz);
-  df[10] = -(P.Jz - P.Jy) * (dwy * wz + wy * dwz) / P.Jx;
-  df[11] = -(P.Jx - P.Jz) * (dwz * wx + wz * dwx) / P.Jy;
-  df[12] = -(P.Jy - P.Jx) * (dwx * wy + wx * dwy) / P.Jz;
+  df[10] = -(P.Jz - P.Jy) * (dwy * wz + wy * dwz) * I.Jx;
+  df[11] = -(P.Jx - P.Jz) * (dwz * wx + wz * dwx) * I.Jy;
+  df[12] = -(P.Jy - P.Jx) * (dwx * wy + wx * dwy) * I.Jz;
 }
 
 // J_x d restricted to rows 7..12 (network inputs are v, omega, q).
@@ -121,14 +130,15 @@ rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, 
   const int xcol = c < 10 ? 3 + c : -1;
   const int ucol = (c >= 10 && c < 14) ? c - 10 : -1;
   const float h = P.arm * 0.70710678118654752f;
+  const QuadInv I = quad_inv(P);
   float fu[13];  // df_F/du_j + J_u e_j (state-independent parts added per stage)
   if (ucol >= 0) {
     const float sx[4] = {-1.f, -1.f, 1.f, 1.f}, sy[4] = {-1.f, 1.f, 1.f, -1.f}, sz[4] = {-1.f, 1.f, -1.f, 1.f};
 #pragma unroll
     for (int i = 0; i < 13; ++i) fu[i] = 0.f;
-    fu[10] = h * sx[ucol] / P.Jx;
-    fu[11] = h * sy[ucol] / P.Jy;
-    fu[12] = P.c_tau * sz[ucol] / P.Jz;
+    fu[10] = h * sx[ucol] * I.Jx;
+    fu[11] = h * sy[ucol] * I.Jy;
+    fu[12] = P.c_tau * sz[ucol] * I.Jz;
 #pragma unroll
     for (int r = 0; r < 6; ++r) fu[7 + r] += J[r * kDin + 10 + ucol];
   }
@@ -147,7 +157,7 @@ rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, 
       ds[i] = ((i == xcol) ? 1.f : 0.f) + cdt * dkp[i];
     }
     // stage derivative of the state
-    nominal_rhs(xs, uk, P, ks);
+    nominal_rhs(xs, uk, P, I, ks);
     float dx[13], r6[6];
 #pragma unroll
     for (int i = 0; i < 13; ++i) dx[i] = xs[i] - xk[i];
@@ -155,16 +165,16 @@ rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, 
 #pragma unroll
     for (int r = 0; r < 6; ++r) ks[7 + r] += yb[r] + r6[r];
     // stage derivative of the tangent
-    nominal_tangent(xs, uk, P, ds, dk);
+    nominal_tangent(xs, uk, P, I, ds, dk);
     residual_tangent(J, ds, r6);
 #pragma unroll
     for (int r = 0; r < 6; ++r) dk[7 + r] += r6[r];
     if (ucol >= 0) {
       // thrust direction at the stage point (the homogeneous q (.) e_z)
       const float qw = xs[3], qx = xs[4], qy = xs[5], qz = xs[6];
-      dk[7] += 2.f * (qx * qz + qw * qy) / P.mass;
-      dk[8] += 2.f * (qy * qz - qw * qx) / P.mass;
-      dk[9] += (qw * qw - qx * qx - qy * qy + qz * qz) / P.mass;
+      dk[7] += 2.f * (qx * qz + qw * qy) * I.m;
+      dk[8] += 2.f * (qy * qz - qw * qx) * I.m;
+      dk[9] += (qw * qw - qx * qx - qy * qy + qz * qz) * I.m;
 #pragma unroll
       for (int i = 7; i < 13; ++i) dk[i] += fu[i];
     }
@@ -282,10 +292,11 @@ rk4_exact_stage_kernel(int n, int stage, QuadConst P, float dt, const float* __r
     ds[i] = ((i == c) ? 1.f : 0.f) + cdt * dprev;
   }
   float ks[13], dk[13], r6[6];
-  nominal_rhs(xs, uk, P, ks);
+  const QuadInv I = quad_inv(P);
+  nominal_rhs(xs, uk, P, I, ks);
 #pragma unroll
   for (int r = 0; r < 6; ++r) ks[7 + r] += yb[r];
-  nominal_tangent(xs, uk, P, ds, dk);
+  nominal_tangent(xs, uk, P, I, ds, dk);
   residual_tangent(J, ds, r6);
 #pragma unroll
   for (int r = 0; r < 6; ++r) dk[7 + r] += r6[r];
@@ -294,12 +305,12 @@ rk4_exact_stage_kernel(int n, int stage, QuadConst P, float dt, const float* __r
     const float h = P.arm * 0.70710678118654752f;
     const float sx[4] = {-1.f, -1.f, 1.f, 1.f}, sy[4] = {-1.f, 1.f, 1.f, -1.f}, sz[4] = {-1.f, 1.f, -1.f, 1.f};
     const float qw = xs[3], qx = xs[4], qy = xs[5], qz = xs[6];
-    dk[7] += 2.f * (qx * qz + qw * qy) / P.mass;
-    dk[8] += 2.f * (qy * qz - qw * qx) / P.mass;
-    dk[9] += (qw * qw - qx * qx - qy * qy + qz * qz) / P.mass;
-    dk[10] += h * sx[j] / P.Jx;
-    dk[11] += h * sy[j] / P.Jy;
-    dk[12] += P.c_tau * sz[j] / P.Jz;
+    dk[7] += 2.f * (qx * qz + qw * qy) * I.m;
+    dk[8] += 2.f * (qy * qz - qw * qx) * I.m;
+    dk[9] += (qw * qw - qx * qx - qy * qy + qz * qz) * I.m;
+    dk[10] += h * sx[j] * I.Jx;
+    dk[11] += h * sy[j] * I.Jy;
+    dk[12] += P.c_tau * sz[j] * I.Jz;
 #pragma unroll
     for (int r = 0; r < 6; ++r) dk[7 + r] += J[r * kDin + 10 + j];
   }

@@ -40,19 +40,33 @@ def flops_per_node(L: int, H: int, d_in: int = 14, d_out: int = 6):
 
 def measured_traffic(config_key: str, kernel_prefix: str):
     """HBM bytes per launch of a kernel from the committed counter summary
-    (profiles/linearize_<config>_*_hbm_traffic.json), only while the kernel source
-    is the one the counters were taken on; else None."""
+    (profiles/linearize_<config>_*_hbm_traffic.json), only while every kernel source
+    the counters were taken on is unchanged; else None."""
     import glob
     import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", f"linearize_{config_key}_*_hbm_traffic.json")):
         rec = json.load(open(path))
-        src = os.path.join(ROOT, rec["source"])
-        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-            return None
+        for src, digest in rec["sources"].items():
+            f = os.path.join(ROOT, src)
+            if not os.path.exists(f) or hashlib.sha256(open(f, "rb").read()).hexdigest() != digest:
+                return None
         for k, v in rec["per_launch"].items():
             if k.split("::")[-1].startswith(kernel_prefix):
                 return v["read_bytes"] + v["write_bytes"]
     return None
+
+
+def copy_probe():
+    """A plain 64 MiB device-to-device copy, three times: the reference kernel whose
+    FETCH_SIZE / WRITE_SIZE counter readings calibrate the HBM traffic figures."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 64 MiB x3", flush=True)
 
 
 def tile_choice(rtn, prec, H, L, n):
@@ -79,6 +93,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the latency, Riccati and training side measurements")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="only run a 64 MiB device copy (counter calibration for the traffic figures)")
     return p.parse_args()
 
 
@@ -183,6 +199,9 @@ def extras(torch, rtn, lin_out, off, stream):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(nodes are independent, so G GPUs would each take a contiguous range of instances)",

@@ -54,6 +54,9 @@ template <int P, int H, bool REV> struct ChainShapeDefault {
 //   V = 2: one wave per SIMD with half the register file and at most 80 KB of
 //          LDS (64 rows, else 32), so that two workgroups share a compute unit
 //          and one's epilogue overlaps the other's matrix work.
+//   V = 3: reverse, bf16/fp8 width 512: one wave per SIMD, 128 rows, all 256
+//          accumulator registers in use -- a quarter less weight traffic from
+//          L2 per matrix product than 96 rows.
 // OCC is the number of waves per SIMD the register budget is sized for.
 template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
   using D = ChainShapeDefault<P, H, REV>;
@@ -65,12 +68,14 @@ template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
                                  (H / 32 / 4) * 2 * 16 <= 128;
   static constexpr int R2 = FITS64 ? 64 : 32;
   static constexpr int NW = V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : 4;
-  static constexpr int R = V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : R2;
+  static constexpr int R =
+      V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : V == 2 ? R2 : 128;
   static constexpr int OCC = V == 2 ? 2 : (NW <= 4 ? 1 : 2);
   static constexpr bool VALID =
       V == 0 || (V == 1 && H >= 512 && R >= 32) ||
       (V == 2 && H >= 512 && R * H * ESZ + (REV ? 7 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
-       (H / 32 / 4) * (R / 32) * 16 <= 128);
+       (H / 32 / 4) * (R / 32) * 16 <= 128) ||
+      (V == 3 && REV && H == 512 && P != P_FP32);
 };
 
 // OCC: waves per SIMD the kernel is built for (1: the whole register file and,
@@ -104,7 +109,7 @@ template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain
   static constexpr int WO_BYTES = WO_IN_LDS ? kDout * WOS * 4 : 0;
   static constexpr int REV_LDS_BYTES = LDS_BYTES + SP_BYTES + WO_BYTES;
   static_assert(MT % NW == 0, "width must split evenly over the waves");
-  static_assert(MTW * RT * 16 <= (OCC == 1 ? 192 : 128), "accumulator budget");
+  static_assert(MTW * RT * 16 <= (OCC == 1 ? 256 : 128), "accumulator budget");
   static_assert(REV_LDS_BYTES <= LDS_CAP || LDS_BYTES <= LDS_CAP, "LDS budget");
 
   // LDS element index of (row tile, K-step, lane, slot-in-step) for an operand with KS K-steps.
@@ -591,7 +596,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
       // with one wave per SIMD there are registers to read all of this wave's
       // activation-derivative runs (16 stash values = 32 or 64 bytes each, kept
       // packed) before their first use
-      constexpr bool PRE = C::kOcc == 1;
+      constexpr bool PRE = C::kOcc == 1 && C::MTW * C::RT <= 12;
       constexpr int PI = PRE ? C::MTW : 1, PR = PRE ? C::RT : 1;
       constexpr int RUN_CH = 16 * (int)sizeof(S) / 16;  // 16-byte chunks per run
       i32x4 spraw[PI][PR][RUN_CH];
@@ -728,6 +733,7 @@ template <int P, int H, int V> hipError_t chain_geom_v(int rev, int occupancy, C
     case 512 * 4: return FN<P, 512, 0>(__VA_ARGS__);           \
     case 512 * 4 + 1: return FN<P, 512, 1>(__VA_ARGS__);       \
     case 512 * 4 + 2: return FN<P, 512, 2>(__VA_ARGS__);       \
+    case 512 * 4 + 3: return FN<P, 512, 3>(__VA_ARGS__);       \
     case 1024 * 4: return FN<P, 1024, 0>(__VA_ARGS__);         \
     case 1024 * 4 + 1: return FN<P, 1024, 1>(__VA_ARGS__);     \
     case 1024 * 4 + 2: return FN<P, 1024, 2>(__VA_ARGS__);     \

@@ -38,10 +38,10 @@ def flops_per_node(L: int, H: int, d_in: int = 14, d_out: int = 6):
     return fwd, rev
 
 
-def measured_traffic(config_key: str, kernel_prefix: str):
-    """HBM bytes per launch of a kernel from the committed counter summary
-    (profiles/linearize_<config>_*_hbm_traffic.json), only while every kernel source
-    the counters were taken on is unchanged; else None."""
+def measured_traffic(config_key: str, kernel_prefix: str, nodes: int):
+    """HBM bytes of a kernel launch over `nodes` nodes, scaled from the committed counter
+    summary (profiles/linearize_<config>_*_hbm_traffic.json, bytes per node), only while
+    every kernel source the counters were taken on is unchanged; else None."""
     import glob
     import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", f"linearize_{config_key}_*_hbm_traffic.json")):
@@ -52,7 +52,7 @@ def measured_traffic(config_key: str, kernel_prefix: str):
                 return None
         for k, v in rec["per_launch"].items():
             if k.split("::")[-1].startswith(kernel_prefix):
-                return v["read_bytes"] + v["write_bytes"]
+                return (v["read_bytes"] + v["write_bytes"]) / rec["nodes_per_launch"] * nodes
     return None
 
 
@@ -247,10 +247,14 @@ def main():
     gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
 
     f_fwd, f_rev = flops_per_node(L, H)
-    rev_ms = kern.get("mlp_reverse_chain", {}).get("avg_ms", float("nan"))
-    fwd_ms = kern.get("mlp_forward_chain", {}).get("avg_ms", float("nan"))
-    rk4_ms = kern.get("rk4_linearize", {}).get("avg_ms", float("nan"))
-    achieved = n * f_rev / (rev_ms * 1e-3) / 1e12
+    nan = {"avg_ms": float("nan"), "total_ms": float("nan"), "calls": 0}
+    krev = kern.get("mlp_reverse_chain", nan)
+    rev_ms = krev["avg_ms"]
+    fwd_ms = kern.get("mlp_forward_chain", nan)["avg_ms"]
+    rk4_ms = kern.get("rk4_linearize", nan)["avg_ms"]
+    launches = max(1, round(krev["calls"] / args.steps))  # large batches run as node chunks
+    # algorithmic flops of all reverse launches over their summed event durations
+    achieved = n * f_rev * args.steps / (krev["total_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     result = {
         "metric": METRIC, "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
@@ -260,10 +264,12 @@ def main():
                    "hidden_layers": L, "width": H, "dt": cfg.dt},
         "roofline": {"bound": "mfma", "kernel": "mlp_reverse_chain", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(args.config, "mlp_reverse_chain"),
-                     "algorithmic_flops_per_launch": n * f_rev, "avg_launch_ms": rev_ms},
-        "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms},
-        "tile_choice": tile_choice(rtn, prec, H, L, n),
+                     "traffic": measured_traffic(args.config, "mlp_reverse_chain", n // launches),
+                     "algorithmic_flops_per_launch": n * f_rev / launches, "avg_launch_ms": rev_ms,
+                     "launches_per_step": launches},
+        "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms,
+                       "note": "average per launch; with two node chunks per step the chunks' kernels overlap"},
+        "tile_choice": tile_choice(rtn, prec, H, L, n // launches),
         "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,
         "host_wall_ms_per_step": wall_ms,
     }

@@ -114,12 +114,24 @@ def time_steps(torch, fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps, wall / steps * 1e3
 
 
-def cpu_baseline(cfg, x, u, Ws, bs, gpu_out, seconds):
-    """The FP64 oracle, as it stands, on a bounded prefix of the same nodes; also the
-    error of the GPU outputs on that prefix against it."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, gpu_K, seconds):
+    """The FP64 oracle, as it stands, on a bounded prefix of the same nodes (all host
+    threads, then one thread); also the error of the GPU outputs on that prefix against
+    it, and of the GPU's fp64 Riccati gains (on the GPU's A_k, B_k, and end to end)."""
     import threadpoolctl
     from oracle.mlp import MLP
     from oracle.rk4 import linearize_affine
+    from oracle.riccati import riccati_batched
     net = MLP(Ws, bs)
     n_sample = min(2048, x.shape[0])
     done, t0 = 0, time.perf_counter()
@@ -132,15 +144,36 @@ def cpu_baseline(cfg, x, u, Ws, bs, gpu_out, seconds):
             break
     elapsed = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    n1 = min(256, n_sample)
+    with threadpoolctl.threadpool_limits(1):
+        done1, t1 = 0, time.perf_counter()
+        while time.perf_counter() - t1 < seconds / 4:
+            linearize_affine(x[:n1], u[:n1], net, cfg.dt)
+            done1 += n1
+        rate1 = done1 / (time.perf_counter() - t1)
     errs = {}
     for name, r in zip(("x_next", "A", "B", "f_D", "J_D"), ref):
         g = gpu_out[name][:n_sample].reshape(n_sample, -1).astype(np.float64)
         rr = r.reshape(n_sample, -1)
         e = np.linalg.norm(g - rr, axis=1) / np.maximum(np.linalg.norm(rr, axis=1), 1e-30)
         errs[name] = {"max": float(e.max()), "p999": float(np.quantile(e, 0.999))}
+    # Riccati gains (Q = I, R = 0.1 I, Q_N = Q) of the instances inside the prefix
+    n_inst = int(np.searchsorted(off, n_sample, side="right")) - 1
+    o = off[:n_inst + 1]
+    Q, R = np.eye(13), 0.1 * np.eye(4)
+    m = int(o[-1])
+    K_same, _, _ = riccati_batched(o, gpu_out["A"][:m].astype(np.float64), gpu_out["B"][:m].astype(np.float64),
+                                   Q, R, Q)
+    K_ref, _, _ = riccati_batched(o, ref[1][:m], ref[2][:m], Q, R, Q)
+    for name, Kr in (("K_same_AB", K_same), ("K_end_to_end", K_ref)):
+        g = gpu_K[:m].reshape(m, -1)
+        rr = Kr.reshape(m, -1)
+        e = np.linalg.norm(g - rr, axis=1) / np.maximum(np.linalg.norm(rr, axis=1), 1e-30)
+        errs[name] = {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "instances": n_inst}
     cpu = {"value": done / elapsed, "unit": "nodes/s", "cores": int(threads), "kind": "oracle",
            "sample": f"first {n_sample} nodes of the workload, fp64 NumPy oracle, repeated for "
-                     f"{elapsed:.1f} s ({done} node linearisations)"}
+                     f"{elapsed:.1f} s ({done} node linearisations)",
+           "single_thread_value": rate1, "cpu_model": cpu_model()}
     return cpu, errs
 
 
@@ -267,8 +300,7 @@ def main():
                      "traffic": measured_traffic(args.config, "mlp_reverse_chain", n // launches),
                      "algorithmic_flops_per_launch": n * f_rev / launches, "avg_launch_ms": rev_ms,
                      "launches_per_step": launches},
-        "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms,
-                       "note": "average per launch; with two node chunks per step the chunks' kernels overlap"},
+        "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms},
         "tile_choice": tile_choice(rtn, prec, H, L, n // launches),
         "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,
         "host_wall_ms_per_step": wall_ms,
@@ -291,7 +323,9 @@ def main():
     if not args.no_extras:
         result["extras"] = extras(torch, rtn, out, off, stream)
     if not args.no_cpu:
-        cpu, errs = cpu_baseline(cfg, x, u, Ws, bs, gpu_out, args.cpu_seconds)
+        ric = rtn.riccati(out["A"], out["B"], np.eye(13), 0.1 * np.eye(4), np.eye(13), offsets=off, stream=stream)
+        torch.cuda.synchronize()
+        cpu, errs = cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, ric["K"].cpu().numpy(), args.cpu_seconds)
         result["cpu_baseline"] = cpu
         result["err_vs_fp64"] = errs
     print(json.dumps(result), flush=True)

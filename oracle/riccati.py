@@ -154,3 +154,84 @@ def lq_rollout_batched(offsets, A, B, K, kff, dx0, c=None):
         ui, xi = lq_rollout(A[a:b], B[a:b], K[a:b], kff[a:b], dx0[i], None if c is None else c[a:b])
         du[a:b], dx[a:b], dxN[i] = ui, xi[:-1], xi[-1]
     return du, dx, dxN
+
+
+# ---------------------------------------------------------------- input box
+# The QP of Sec. IV-A with the inequality rows eq. (3) restricted to the input
+# box: lo_k <= du_k <= hi_k (for 0 <= u <= u_max: lo = -u_k, hi = u_max - u_k).
+
+def condense(A, B, Q, R, QN, dx0, c=None, q=None, r=None, qN=None):
+    """Eliminate the states: dx = S du + s (stacked dx_1..dx_N), so the QP becomes
+    min 1/2 du^T H du + h^T du over the stacked du (N*4).  Returns H, h, S, s."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    N, nx, nu = B.shape
+    c = np.zeros((N, nx)) if c is None else np.asarray(c, dtype=np.float64)
+    q = np.zeros((N, nx)) if q is None else np.asarray(q, dtype=np.float64)
+    r = np.zeros((N, nu)) if r is None else np.asarray(r, dtype=np.float64)
+    qN = np.zeros(nx) if qN is None else np.asarray(qN, dtype=np.float64)
+    S = np.zeros((N * nx, N * nu))  # rows: dx_{k+1}
+    s = np.zeros(N * nx)
+    x_prev, S_prev = np.asarray(dx0, dtype=np.float64), np.zeros((nx, N * nu))
+    for k in range(N):
+        S_k = A[k] @ S_prev
+        S_k[:, k * nu:(k + 1) * nu] += B[k]
+        x_k = A[k] @ x_prev + c[k]
+        S[k * nx:(k + 1) * nx], s[k * nx:(k + 1) * nx] = S_k, x_k
+        S_prev, x_prev = S_k, x_k
+    # state cost weights of dx_1..dx_N (dx_0 is fixed); linear terms q_k act on dx_k
+    W = np.zeros((N * nx, N * nx))
+    w = np.zeros(N * nx)
+    for k in range(1, N):
+        W[(k - 1) * nx:k * nx, (k - 1) * nx:k * nx] = Q
+        w[(k - 1) * nx:k * nx] = q[k]
+    W[(N - 1) * nx:, (N - 1) * nx:] = QN
+    w[(N - 1) * nx:] = qN
+    H = S.T @ W @ S + np.kron(np.eye(N), R)
+    h = S.T @ (W @ s + w) + r.reshape(-1)
+    return H, h, S, s
+
+
+def box_lq(A, B, Q, R, QN, dx0, lo, hi, c=None, q=None, r=None, qN=None):
+    """Exact minimiser of the box-constrained LQ of one instance: the condensed QP
+    written as a bounded least-squares problem (H = L L^T) and solved by SciPy's
+    bounded-variable least squares (an active-set method that ends at the exact
+    solution).  Returns du (N,4) and dx (N+1,13)."""
+    import scipy.linalg
+    import scipy.optimize
+    N, nx, nu = np.asarray(B).shape
+    H, h, S, s = condense(A, B, Q, R, QN, dx0, c, q, r, qN)
+    L = np.linalg.cholesky(H)
+    # 1/2 x^T H x + h^T x = 1/2 |L^T x + L^{-1} h|^2 + const
+    rhs = -scipy.linalg.solve_triangular(L, h, lower=True)
+    res = scipy.optimize.lsq_linear(L.T, rhs, bounds=(np.asarray(lo).reshape(-1), np.asarray(hi).reshape(-1)),
+                                    method="bvls", tol=1e-14, lsmr_tol=None)
+    du = res.x
+    dx = np.concatenate([np.asarray(dx0, dtype=np.float64), S @ du + s]).reshape(N + 1, nx)
+    return du.reshape(N, nu), dx
+
+
+def box_lq_bruteforce(A, B, Q, R, QN, dx0, lo, hi, c=None, q=None, r=None, qN=None):
+    """Enumerate every assignment of each input component to {lower bound, upper
+    bound, free}, solve the equality-reduced QP, keep the feasible candidate with the
+    lowest cost.  Tiny instances only (3^(4N) systems)."""
+    import itertools
+    N, nx, nu = np.asarray(B).shape
+    H, h, S, s = condense(A, B, Q, R, QN, dx0, c, q, r, qN)
+    lo, hi = np.asarray(lo).reshape(-1), np.asarray(hi).reshape(-1)
+    nv = N * nu
+    best, best_x = np.inf, None
+    for assign in itertools.product((0, 1, 2), repeat=nv):
+        a = np.array(assign)
+        x = np.where(a == 0, lo, np.where(a == 1, hi, 0.0))
+        free = a == 2
+        if free.any():
+            Hff = H[np.ix_(free, free)]
+            x[free] = np.linalg.solve(Hff, -(h[free] + H[np.ix_(free, ~free)] @ x[~free]))
+            if np.any(x[free] < lo[free] - 1e-12) or np.any(x[free] > hi[free] + 1e-12):
+                continue
+        f = 0.5 * x @ H @ x + h @ x
+        if f < best - 1e-13:
+            best, best_x = f, x
+    dx = np.concatenate([np.asarray(dx0, dtype=np.float64), S @ best_x + s]).reshape(N + 1, nx)
+    return best_x.reshape(N, nu), dx

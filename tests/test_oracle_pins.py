@@ -16,7 +16,8 @@ from oracle.quadrotor import (nominal_f, nominal_jac, quat_mul, quat_conj, quat_
                               rotor_positions, ROTOR_SPIN, body_torque)
 from oracle.mlp import MLP, pack_input, residual_in_state, silu_prime
 from oracle.rk4 import (linearize_affine, linearize_exact, affine_phi, exact_phi, rk4_step)
-from oracle.riccati import riccati, riccati_batched, kkt_bruteforce, lq_rollout, lq_rollout_batched
+from oracle.riccati import (riccati, riccati_batched, kkt_bruteforce, lq_rollout, lq_rollout_batched, box_lq,
+                            box_lq_bruteforce, condense)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DT = 0.05
@@ -406,3 +407,49 @@ def test_lq_rollout_batched_ranges():
         np.testing.assert_allclose(du[a:b], du_ref, atol=1e-10)
         np.testing.assert_allclose(dx[a:b], dx_ref[:-1], atol=1e-10)
         np.testing.assert_allclose(dxN[i], dx_ref[-1], atol=1e-10)
+
+
+# ---------------------------------------------------------------- input box (QP with eq. (3) on u)
+
+def test_box_lq_without_active_bounds_is_the_unconstrained_minimiser():
+    A, B, c, q, r, qN, Q, R, QN = _random_lq(4, seed=31)
+    dx0 = np.random.default_rng(2).normal(size=13)
+    du_ref, dx_ref = kkt_bruteforce(A, B, Q, R, QN, dx0, c, q, r, qN)
+    big = np.full((4, 4), 1e9)
+    du, dx = box_lq(A, B, Q, R, QN, dx0, -big, big, c, q, r, qN)
+    np.testing.assert_allclose(du, du_ref, atol=1e-10)
+    np.testing.assert_allclose(dx, dx_ref, atol=1e-10)
+
+
+@pytest.mark.parametrize("N,seed", [(1, 1), (2, 2), (2, 3)])
+def test_box_lq_matches_active_set_enumeration(N, seed):
+    A, B, c, q, r, qN, Q, R, QN = _random_lq(N, seed=40 + seed)
+    rng = np.random.default_rng(seed)
+    dx0 = rng.normal(size=13)
+    lo, hi = -rng.uniform(0.05, 0.6, size=(N, 4)), rng.uniform(0.05, 0.6, size=(N, 4))
+    du, dx = box_lq(A, B, Q, R, QN, dx0, lo, hi, c, q, r, qN)
+    du_b, dx_b = box_lq_bruteforce(A, B, Q, R, QN, dx0, lo, hi, c, q, r, qN)
+    np.testing.assert_allclose(du, du_b, atol=1e-10)
+    np.testing.assert_allclose(dx, dx_b, atol=1e-10)
+    assert np.sum(np.isclose(du, lo) | np.isclose(du, hi)) > 0  # the box is active somewhere
+
+
+def test_box_lq_kkt_conditions():
+    """Stationarity with sign-correct multipliers: the condensed gradient vanishes on free
+    components, is >= 0 at lower bounds and <= 0 at upper bounds; dynamics hold."""
+    N = 6
+    A, B, c, q, r, qN, Q, R, QN = _random_lq(N, seed=51)
+    rng = np.random.default_rng(5)
+    dx0 = 3 * rng.normal(size=13)
+    lo, hi = np.full((N, 4), -0.2), np.full((N, 4), 0.25)
+    du, dx = box_lq(A, B, Q, R, QN, dx0, lo, hi, c, q, r, qN)
+    H, h, S, s = condense(A, B, Q, R, QN, dx0, c, q, r, qN)
+    g = H @ du.reshape(-1) + h
+    x, l, u = du.reshape(-1), lo.reshape(-1), hi.reshape(-1)
+    at_lo, at_hi = np.isclose(x, l, atol=1e-12), np.isclose(x, u, atol=1e-12)
+    free = ~(at_lo | at_hi)
+    assert at_lo.any() and at_hi.any() and free.any()
+    assert np.all(np.abs(g[free]) < 1e-9)
+    assert np.all(g[at_lo] > -1e-9) and np.all(g[at_hi] < 1e-9)
+    for k in range(N):
+        np.testing.assert_allclose(dx[k + 1], A[k] @ dx[k] + B[k] @ du[k] + c[k], atol=1e-10)

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "linearize", "linearize_exact", "riccati", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "linearize", "linearize_exact", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -334,6 +334,51 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
                              _dev(K, f64, (n, 4, 13), "K"), _dev(kff, f64, (n, 4), "kff"),
                              _dev(P, f64, (n, 13, 13), "P") if P is not None else None,
                              _stream(stream)), "rtn_riccati")
+    return out
+
+
+def riccati_box(A, B, Q, R, QN, dx0, du_lo, du_hi, offsets=None, c=None, q=None, r=None, qN=None,
+                rho: float = 1.0, max_iter: int = 500, tol: float = 1e-8, want_dx: bool = True,
+                out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
+    """rtn_riccati_box: the LQ step with the input box du_lo <= du <= du_hi (ADMM).
+    Returns du [n,4], iters [n_inst] (int32) and optionally dx [n,13], dxN [n_inst,13]."""
+    torch = _torch()
+    n = A.shape[0]
+    dev = A.device
+    if offsets is None:
+        n_inst, off_ptr = 1, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    if out is None:
+        out = {}
+    def get(name, shape, dtype=torch.float64):
+        t = out.get(name)
+        if t is None:
+            t = out[name] = torch.empty(shape, dtype=dtype, device=dev)
+        return t
+    f64 = torch.float64
+    du = get("du", (n, 4))
+    iters = get("iters", (n_inst,), torch.int32)
+    dx = get("dx", (n, 13)) if want_dx else None
+    dxN = get("dxN", (n_inst, 13)) if want_dx else None
+    Qh = np.ascontiguousarray(Q, dtype=np.float64)
+    Rh = np.ascontiguousarray(R, dtype=np.float64)
+    QNh = np.ascontiguousarray(QN, dtype=np.float64)
+    check(load().rtn_riccati_box(n_inst, off_ptr, n, _dev(A, torch.float32, (n, 13, 13), "A"),
+                                 _dev(B, torch.float32, (n, 13, 4), "B"),
+                                 _dev(c, f64, (n, 13), "c") if c is not None else None,
+                                 Qh.ctypes.data_as(ctypes.c_void_p), Rh.ctypes.data_as(ctypes.c_void_p),
+                                 QNh.ctypes.data_as(ctypes.c_void_p),
+                                 _dev(q, f64, (n, 13), "q") if q is not None else None,
+                                 _dev(r, f64, (n, 4), "r") if r is not None else None,
+                                 _dev(qN, f64, (n_inst, 13), "qN") if qN is not None else None,
+                                 _dev(dx0, f64, (n_inst, 13), "dx0"), _dev(du_lo, f64, (n, 4), "du_lo"),
+                                 _dev(du_hi, f64, (n, 4), "du_hi"), float(rho), int(max_iter), float(tol),
+                                 _dev(du, f64, (n, 4), "du"),
+                                 _dev(dx, f64, (n, 13), "dx") if dx is not None else None,
+                                 _dev(dxN, f64, (n_inst, 13), "dxN") if dxN is not None else None,
+                                 _dev(iters, torch.int32, (n_inst,), "iters"), _stream(stream)), "rtn_riccati_box")
     return out
 
 

@@ -215,6 +215,225 @@ hipError_t launch_lq_rollout(int n_inst, const int* offsets, const float* A, con
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Input box lo_k <= du_k <= hi_k (the input rows of eq. (3)) by ADMM on the split
+// du = z, z in the box (scaled dual y):
+//   du-step: the LQ above with R + rho I and r_k - rho (z_k - y_k) -- the matrix
+//            recursion (K_k, P_k) does not change between iterations, so it is
+//            computed once (riccati_kernel) and each iteration is one backward pass
+//            of the vectors and one rollout;
+//   z-step : z_k = clip(du_k + y_k, lo_k, hi_k);   y-step: y_k += du_k - z_k.
+// Stops when max |du - z| and rho max |z - z_prev| are both below tol.  The
+// returned inputs are z (inside the box) and the states rolled out with them.
+struct BoxArgs {
+  const int* offsets;
+  const float* A;
+  const float* B;
+  const double* c;   // nullable
+  const double* QN;  // 13x13
+  const double* Rt;  // 4x4, R + rho I
+  const double* q;   // nullable [n][13]
+  const double* r;   // nullable [n][4]
+  const double* qN;  // nullable [n_inst][13]
+  const double* K;   // [n][4][13] of R + rho I
+  const double* P;   // [n][13][13] of R + rho I
+  const double* dx0; // [n_inst][13]
+  const double* lo;  // [n][4]
+  const double* hi;  // [n][4]
+  double rho, tol;
+  int max_iter;
+  double* ws;        // [n][28]: Quu^-1 (16), z (4), y (4), kff (4)
+  double* du;        // [n][4]
+  double* dx;        // nullable [n][13]
+  double* dxN;       // nullable [n_inst][13]
+  int* iters;        // nullable [n_inst]
+};
+
+constexpr int kBoxWs = kBoxWsDoubles;
+
+__global__ void __launch_bounds__(64) box_admm_kernel(BoxArgs a) {
+  __shared__ double sP[NX * NX], sPB[NX * NU], sQuu[NU * NU];
+  __shared__ double sp[NX], sg[NX], sqx[NX], squ[NU], sx[NX], su[NU];
+  __shared__ double sres[2][NU];
+  __shared__ int sdone;
+  const int inst = blockIdx.x, t = threadIdx.x;
+  const int k0 = a.offsets[inst], k1 = a.offsets[inst + 1];
+  auto Pnext = [&](int k) { return k + 1 < k1 ? a.P + (size_t)(k + 1) * NX * NX : a.QN; };
+  // set-up: Quu_k^-1 = (R + rho I + B^T P_{k+1} B)^-1, z_k = clip(0), y_k = 0
+  for (int k = k0; k < k1; ++k) {
+    const float* Bk = a.B + (size_t)k * NX * NU;
+    const double* Pn = Pnext(k);
+    if (t < NX * NU) {
+      const int m = t / NU, j = t % NU;
+      double s = 0.0;
+      for (int l = 0; l < NX; ++l) s += Pn[m * NX + l] * (double)Bk[l * NU + j];
+      sPB[t] = s;
+    }
+    __syncthreads();
+    if (t < NU * NU) {
+      const int i = t / NU, j = t % NU;
+      double s = a.Rt[t];
+      for (int m = 0; m < NX; ++m) s += (double)Bk[m * NU + i] * sPB[m * NU + j];
+      sQuu[t] = s;
+    }
+    __syncthreads();
+    if (t < NU) {  // column t of the inverse: Cholesky solve of Quu x = e_t (symmetrised)
+      double L[NU][NU] = {};
+      for (int j = 0; j < NU; ++j) {
+        double d = sQuu[j * NU + j];
+        for (int m = 0; m < j; ++m) d -= L[j][m] * L[j][m];
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < NU; ++i) {
+          double s = 0.5 * (sQuu[i * NU + j] + sQuu[j * NU + i]);
+          for (int m = 0; m < j; ++m) s -= L[i][m] * L[j][m];
+          L[i][j] = s / L[j][j];
+        }
+      }
+      double y[NU], x[NU];
+      for (int i = 0; i < NU; ++i) {
+        double s = i == t ? 1.0 : 0.0;
+        for (int m = 0; m < i; ++m) s -= L[i][m] * y[m];
+        y[i] = s / L[i][i];
+      }
+      for (int i = NU - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int m = i + 1; m < NU; ++m) s -= L[m][i] * x[m];
+        x[i] = s / L[i][i];
+      }
+      double* w = a.ws + (size_t)k * kBoxWs;
+      for (int i = 0; i < NU; ++i) w[i * NU + t] = x[i];
+      const double lo = a.lo[(size_t)k * NU + t], hi = a.hi[(size_t)k * NU + t];
+      w[16 + t] = fmin(fmax(0.0, lo), hi);
+      w[20 + t] = 0.0;
+    }
+    __syncthreads();
+  }
+  int it = 0;
+  for (; it < a.max_iter; ++it) {
+    // backward pass of the linear terms
+    if (t < NX) sp[t] = a.qN ? a.qN[(size_t)inst * NX + t] : 0.0;
+    __syncthreads();
+    for (int k = k1 - 1; k >= k0; --k) {
+      const float* Ak = a.A + (size_t)k * NX * NX;
+      const float* Bk = a.B + (size_t)k * NX * NU;
+      const double* Kk = a.K + (size_t)k * NU * NX;
+      double* w = a.ws + (size_t)k * kBoxWs;
+      const double* Pn = Pnext(k);
+      if (t < NX) {
+        double s = sp[t];
+        if (a.c)
+          for (int l = 0; l < NX; ++l) s += Pn[t * NX + l] * a.c[(size_t)k * NX + l];
+        sg[t] = s;
+      }
+      __syncthreads();
+      if (t < NX) {
+        double s = a.q ? a.q[(size_t)k * NX + t] : 0.0;
+        for (int m = 0; m < NX; ++m) s += (double)Ak[m * NX + t] * sg[m];
+        sqx[t] = s;
+      } else if (t >= 16 && t < 16 + NU) {
+        const int i = t - 16;
+        double s = (a.r ? a.r[(size_t)k * NU + i] : 0.0) - a.rho * (w[16 + i] - w[20 + i]);
+        for (int m = 0; m < NX; ++m) s += (double)Bk[m * NU + i] * sg[m];
+        squ[i] = s;
+      }
+      __syncthreads();
+      if (t < NX) {
+        double s = sqx[t];
+        for (int i = 0; i < NU; ++i) s += Kk[i * NX + t] * squ[i];
+        sp[t] = s;
+      } else if (t >= 16 && t < 16 + NU) {
+        const int i = t - 16;
+        double s = 0.0;
+        for (int j = 0; j < NU; ++j) s -= w[i * NU + j] * squ[j];
+        w[24 + i] = s;
+      }
+      __syncthreads();
+    }
+    // rollout, projection, dual update
+    if (t < NX) sx[t] = a.dx0[(size_t)inst * NX + t];
+    double rp = 0.0, rd = 0.0;
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+      const float* Ak = a.A + (size_t)k * NX * NX;
+      const float* Bk = a.B + (size_t)k * NX * NU;
+      const double* Kk = a.K + (size_t)k * NU * NX;
+      double* w = a.ws + (size_t)k * kBoxWs;
+      if (t >= 16 && t < 16 + NU) {
+        const int i = t - 16;
+        double d = w[24 + i];
+        for (int j = 0; j < NX; ++j) d += Kk[i * NX + j] * sx[j];
+        su[i] = d;
+        const double lo = a.lo[(size_t)k * NU + i], hi = a.hi[(size_t)k * NU + i];
+        const double zn = fmin(fmax(d + w[20 + i], lo), hi);
+        rp = fmax(rp, fabs(d - zn));
+        rd = fmax(rd, a.rho * fabs(zn - w[16 + i]));
+        w[20 + i] += d - zn;
+        w[16 + i] = zn;
+      }
+      __syncthreads();
+      double nx = 0.0;
+      if (t < NX) {
+        nx = a.c ? a.c[(size_t)k * NX + t] : 0.0;
+        for (int j = 0; j < NX; ++j) nx += (double)Ak[t * NX + j] * sx[j];
+        for (int j = 0; j < NU; ++j) nx += (double)Bk[t * NU + j] * su[j];
+      }
+      __syncthreads();
+      if (t < NX) sx[t] = nx;
+      __syncthreads();
+    }
+    if (t >= 16 && t < 16 + NU) {
+      sres[0][t - 16] = rp;
+      sres[1][t - 16] = rd;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double mp = 0.0, md = 0.0;
+      for (int i = 0; i < NU; ++i) {
+        mp = fmax(mp, sres[0][i]);
+        md = fmax(md, sres[1][i]);
+      }
+      sdone = (mp < a.tol && md < a.tol) ? 1 : 0;
+    }
+    __syncthreads();
+    if (sdone) {
+      ++it;
+      break;
+    }
+  }
+  // outputs: the box-feasible inputs z and the states they produce
+  if (t < NX) sx[t] = a.dx0[(size_t)inst * NX + t];
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    const float* Ak = a.A + (size_t)k * NX * NX;
+    const float* Bk = a.B + (size_t)k * NX * NU;
+    const double* w = a.ws + (size_t)k * kBoxWs;
+    if (t < NX && a.dx) a.dx[(size_t)k * NX + t] = sx[t];
+    if (t >= 16 && t < 16 + NU) a.du[(size_t)k * NU + (t - 16)] = w[16 + (t - 16)];
+    double nx = 0.0;
+    if (t < NX) {
+      nx = a.c ? a.c[(size_t)k * NX + t] : 0.0;
+      for (int j = 0; j < NX; ++j) nx += (double)Ak[t * NX + j] * sx[j];
+      for (int j = 0; j < NU; ++j) nx += (double)Bk[t * NU + j] * w[16 + j];
+    }
+    __syncthreads();
+    if (t < NX) sx[t] = nx;
+    __syncthreads();
+  }
+  if (t < NX && a.dxN) a.dxN[(size_t)inst * NX + t] = sx[t];
+  if (t == 0 && a.iters) a.iters[inst] = it;
+}
+
+hipError_t launch_box_admm(int n_inst, const int* offsets, const float* A, const float* B, const double* c,
+                           const double* QN, const double* Rt, const double* q, const double* r, const double* qN,
+                           const double* K, const double* P, const double* dx0, const double* lo, const double* hi,
+                           double rho, double tol, int max_iter, double* ws, double* du, double* dx, double* dxN,
+                           int* iters, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  BoxArgs a{offsets, A, B, c, QN, Rt, q, r, qN, K, P, dx0, lo, hi, rho, tol, max_iter, ws, du, dx, dxN, iters};
+  box_admm_kernel<<<n_inst, 64, 0, st>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const double* R, const double* QN,
                           const float* A, const float* B, const double* c, const double* q, const double* r,
                           const double* qN, double* K, double* kff, double* P, hipStream_t st) {

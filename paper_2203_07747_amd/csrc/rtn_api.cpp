@@ -550,6 +550,68 @@ extern "C" rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, i
   return RTN_OK;
 }
 
+extern "C" rtn_status rtn_riccati_box(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes, const float* A,
+                                      const float* B, const double* c, const double* Q_host, const double* R_host,
+                                      const double* QN_host, const double* q, const double* r, const double* qN,
+                                      const double* dx0, const double* du_lo, const double* du_hi, double rho,
+                                      int32_t max_iter, double tol, double* du, double* dx, double* dxN,
+                                      int32_t* iters, void* stream) {
+  rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
+  if (s) return s;
+  if (!Q_host || !R_host || !QN_host) return fail(RTN_EINVAL, "Q_host, R_host and QN_host are required");
+  for (int i = 0; i < 13 * 13; ++i)
+    if (!std::isfinite(Q_host[i]) || !std::isfinite(QN_host[i])) return fail(RTN_EINVAL, "Q or Q_N is not finite");
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(R_host[i])) return fail(RTN_EINVAL, "R is not finite");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(RTN_EINVAL, "rho must be positive and finite");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(RTN_EINVAL, "tol must be positive and finite");
+  if (max_iter < 1) return fail(RTN_EINVAL, "max_iter must be at least 1 (got %d)", max_iter);
+  if (n_nodes == 0) return RTN_OK;
+  if (!A || !B || !dx0 || !du_lo || !du_hi) return fail(RTN_EINVAL, "A, B, dx0, du_lo and du_hi must be device pointers");
+  if (!du) return fail(RTN_EINVAL, "du must be a device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  // one stream-ordered scratch block: Q, R + rho I, Q_N | offsets | K, kff, P, ADMM state
+  const size_t nd = 169 + 16 + 169;
+  const size_t off_bytes = ((size_t)(n_inst + 1) * 4 + 15) / 16 * 16;
+  const size_t per_node = 52 + 4 + 169 + kBoxWsDoubles;
+  std::vector<char> host(nd * 8 + off_bytes);
+  double* hd = reinterpret_cast<double*>(host.data());
+  memcpy(hd, Q_host, 169 * 8);
+  for (int i = 0; i < 16; ++i) hd[169 + i] = R_host[i] + ((i % 5 == 0) ? rho : 0.0);
+  memcpy(hd + 185, QN_host, 169 * 8);
+  int32_t* off = reinterpret_cast<int32_t*>(host.data() + nd * 8);
+  if (offsets_host) {
+    memcpy(off, offsets_host, (size_t)(n_inst + 1) * 4);
+  } else {
+    off[0] = 0;
+    off[1] = n_nodes;
+  }
+  const size_t bytes = host.size() + (size_t)n_nodes * per_node * 8;
+  void* dev = nullptr;
+  hipError_t e = hipMallocAsync(&dev, bytes, st);
+  if (e != hipSuccess) return fail(RTN_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+  e = hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  const double* d = reinterpret_cast<const double*>(dev);
+  const int* doff = reinterpret_cast<const int*>(static_cast<char*>(dev) + nd * 8);
+  double* K = reinterpret_cast<double*>(static_cast<char*>(dev) + host.size());
+  double* kff = K + (size_t)n_nodes * 52;
+  double* P = kff + (size_t)n_nodes * 4;
+  double* ws = P + (size_t)n_nodes * 169;
+  if (e == hipSuccess) {
+    ProfScope ps("riccati", st);
+    e = launch_riccati(n_inst, doff, d, d + 169, d + 185, A, B, c, q, r, qN, K, kff, P, st);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps("box_admm", st);
+    e = launch_box_admm(n_inst, doff, A, B, c, d + 185, d + 169, q, r, qN, K, P, dx0, du_lo, du_hi, rho, tol,
+                        max_iter, ws, du, dx, dxN, iters, st);
+  }
+  hipError_t e2 = hipFreeAsync(dev, st);
+  if (e != hipSuccess) return hip_fail(e, "rtn_riccati_box");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return RTN_OK;
+}
+
 extern "C" rtn_status rtn_lq_rollout(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
                                      const float* A, const float* B, const double* c, const double* K,
                                      const double* kff, const double* dx0, double* dx, double* du, double* dxN,

@@ -113,6 +113,20 @@ def test_riccati_validation(lib):
                            z, z, None, None) == RTN_EINVAL
 
 
+def test_riccati_box_validation(lib):
+    Q = np.eye(13); R = 0.1 * np.eye(4)
+    qp = Q.ctypes.data_as(ctypes.c_void_p); rp = R.ctypes.data_as(ctypes.c_void_p)
+    z = ctypes.c_void_p(16)
+    args = lambda n, rho, it, tol, du=z: (1, None, n, z, z, None, qp, rp, qp, None, None, None, z, z, z,
+                                         rho, it, tol, du, None, None, None, None)
+    assert lib.rtn_riccati_box(*args(0, 1.0, 10, 1e-8)) == RTN_OK
+    assert lib.rtn_riccati_box(*args(3, 0.0, 10, 1e-8)) == RTN_EINVAL       # rho
+    assert lib.rtn_riccati_box(*args(3, float("nan"), 10, 1e-8)) == RTN_EINVAL
+    assert lib.rtn_riccati_box(*args(3, 1.0, 0, 1e-8)) == RTN_EINVAL        # max_iter
+    assert lib.rtn_riccati_box(*args(3, 1.0, 10, -1.0)) == RTN_EINVAL       # tol
+    assert lib.rtn_riccati_box(*args(3, 1.0, 10, 1e-8, None)) == RTN_EINVAL  # du
+
+
 def test_lq_rollout_validation(lib):
     z = ctypes.c_void_p(16)
     assert lib.rtn_lq_rollout(1, None, 0, None, None, None, None, None, None, None, None, None, None) == RTN_OK

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from workload import config_workload, sample_horizons, offsets_from_horizons
-from oracle.riccati import riccati_batched, kkt_bruteforce, lq_rollout_batched
+from oracle.riccati import riccati_batched, kkt_bruteforce, lq_rollout_batched, box_lq
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +131,60 @@ def test_lq_rollout_matches_oracle_and_kkt(torch):
         du_ref, dx_ref = kkt_bruteforce(A64[a:b], B64[a:b], Q, R, QN, dx0[i], c[a:b], q[a:b], r[a:b])
         np.testing.assert_allclose(out["du"].cpu().numpy()[a:b], du_ref, atol=1e-9)
         np.testing.assert_allclose(out["dxN"].cpu().numpy()[i], dx_ref[-1], atol=1e-9)
+
+
+def test_box_constrained_lq_matches_exact_minimiser(torch):
+    """rtn_riccati_box (ADMM, converged to 1e-11) on ragged instances against the oracle's
+    exact box-QP minimiser; the inputs stay inside the box and the states are their rollout."""
+    import paper_2203_07747_amd as rtn
+    hz = sample_horizons(23, 1, 14, seed=8)
+    off = offsets_from_horizons(hz)
+    n, ni = int(off[-1]), len(hz)
+    A, B, rng = random_lq(n, 5)
+    c = rng.normal(size=(n, 13)) * 0.1
+    q = rng.normal(size=(n, 13)); r = rng.normal(size=(n, 4)); qN = rng.normal(size=(ni, 13))
+    dx0 = 2 * rng.normal(size=(ni, 13))
+    lo = -rng.uniform(0.1, 0.4, size=(n, 4)); hi = rng.uniform(0.1, 0.4, size=(n, 4))
+    Q = np.eye(13); R = 0.1 * np.eye(4); QN = np.eye(13)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    print(f"[gpu] riccati_box n={n} n_inst={ni}", flush=True)
+    out = rtn.riccati_box(dev(A), dev(B), Q, R, QN, dev(dx0), dev(lo), dev(hi), offsets=off, c=dev(c), q=dev(q),
+                          r=dev(r), qN=dev(qN), rho=1.0, max_iter=20000, tol=1e-11)
+    torch.cuda.synchronize()
+    du, dx, dxN = out["du"].cpu().numpy(), out["dx"].cpu().numpy(), out["dxN"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    print(f"  iterations: max {iters.max()} median {np.median(iters)}", flush=True)
+    assert np.all(iters < 20000)
+    assert np.all(du >= lo - 1e-12) and np.all(du <= hi + 1e-12)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    active = 0
+    for i in range(ni):
+        a, b = int(off[i]), int(off[i + 1])
+        du_ref, dx_ref = box_lq(A64[a:b], B64[a:b], Q, R, QN, dx0[i], lo[a:b], hi[a:b], c[a:b], q[a:b], r[a:b],
+                                qN[i])
+        np.testing.assert_allclose(du[a:b], du_ref, atol=1e-8)
+        np.testing.assert_allclose(dx[a:b], dx_ref[:-1], atol=1e-7)
+        np.testing.assert_allclose(dxN[i], dx_ref[-1], atol=1e-7)
+        active += int(np.sum(np.isclose(du_ref, lo[a:b]) | np.isclose(du_ref, hi[a:b])))
+    assert active > 0
+
+
+def test_box_lq_with_inactive_box_equals_unconstrained_step(torch):
+    import paper_2203_07747_amd as rtn
+    hz = sample_horizons(9, 1, 10, seed=9)
+    off = offsets_from_horizons(hz)
+    n, ni = int(off[-1]), len(hz)
+    A, B, rng = random_lq(n, 6)
+    c = rng.normal(size=(n, 13)) * 0.1
+    dx0 = rng.normal(size=(ni, 13))
+    Q = np.eye(13); R = 0.1 * np.eye(4); QN = np.eye(13)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    big = np.full((n, 4), 1e6)
+    At, Bt, ct = dev(A), dev(B), dev(c)
+    box = rtn.riccati_box(At, Bt, Q, R, QN, dev(dx0), dev(-big), dev(big), offsets=off, c=ct, rho=1.0,
+                          max_iter=5000, tol=1e-12)
+    ric = rtn.riccati(At, Bt, Q, R, QN, offsets=off, c=ct)
+    roll = rtn.lq_rollout(At, Bt, ric["K"], ric["kff"], dev(dx0), offsets=off, c=ct)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(box["du"].cpu().numpy(), roll["du"].cpu().numpy(), atol=1e-9)
+    np.testing.assert_allclose(box["dxN"].cpu().numpy(), roll["dxN"].cpu().numpy(), atol=1e-8)

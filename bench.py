@@ -215,6 +215,19 @@ def extras(torch, rtn, lin_out, off, stream):
     ms, _ = time_steps(torch, f, 10, 2, stream)
     res["riccati_fp64"] = {"ms_per_call": ms, "instances": int(len(off) - 1),
                            "nodes_per_s": float(off[-1]) / (ms * 1e-3)}
+    # the same LQ with the input box 0 <= u_k + du_k <= 4 around hover inputs (ADMM, rho 1, tol 1e-6)
+    n_all = int(off[-1])
+    g = torch.Generator(device="cuda").manual_seed(1)
+    dx0 = torch.randn((len(off) - 1, 13), device="cuda", dtype=torch.float64, generator=g) * 0.5
+    uk = torch.full((n_all, 4), 9.81 / 4, device="cuda", dtype=torch.float64)
+    lo, hi = (-uk).contiguous(), (4.0 - uk).contiguous()
+    bout = {}
+    f = lambda: rtn.riccati_box(lin_out["A"], lin_out["B"], Q, R, Q, dx0, lo, hi, offsets=off, rho=1.0,
+                                max_iter=200, tol=1e-6, out=bout, stream=stream)
+    ms, _ = time_steps(torch, f, 5, 1, stream)
+    it = bout["iters"].cpu().numpy()
+    res["riccati_box_fp64"] = {"ms_per_call": ms, "instances": int(len(off) - 1),
+                               "iterations_max": int(it.max()), "iterations_median": float(np.median(it))}
     Ws, bs = xp(TRAIN["n_hidden"], TRAIN["width"], seed=0)
     m = rtn.Model(Ws, bs)
     B = TRAIN["batch"]

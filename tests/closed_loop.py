@@ -7,6 +7,7 @@ horizontal circle (the feedback loop of Sec. IV-B around the QP of Sec. IV-A):
   2. defects c_k = phi-bar_k - x_{k+1} (x_N: the iterate's terminal state) and the
      gradient terms of the tracking cost q_k = Q (x_k - x_ref,k), r_k = R (u_k - u_hover)
   3. rtn_riccati -> K_k, kff_k;  rtn_lq_rollout from dx_0 = x_plant - x_0 -> dx_k, du_k
+     (with ``box=True`` instead rtn_riccati_box with 0 <= u_k + du_k <= u_max)
   4. apply u = clip(u_0 + du_0, 0, u_max) to the plant: one RK4 step of the drag-augmented
      synthetic quadrotor with per-step acceleration noise (the training data's simulator)
   5. record the model's one-step prediction phi-bar_0 + A_0 dx_0 + B_0 (u - u_0) against
@@ -38,7 +39,7 @@ def circle_reference(t: np.ndarray, radius, omega, phase) -> np.ndarray:
 
 
 def run(torch, rtn, model, prec: str, n_inst: int = 4096, N: int = 20, dt: float = 0.05,
-        steps: int = 40, seed: int = 5, noise_std: float = 0.05, device: str = "cuda"):
+        steps: int = 40, seed: int = 5, noise_std: float = 0.05, device: str = "cuda", box: bool = False):
     rng = np.random.default_rng(seed)
     radius = rng.uniform(2.0, 4.0, n_inst)
     speed = rng.uniform(2.0, 4.0, n_inst)
@@ -67,9 +68,15 @@ def run(torch, rtn, model, prec: str, n_inst: int = 4096, N: int = 20, dt: float
         qv = ((Xit - ref[:, :N]) @ Qt).reshape(-1, 13).contiguous()
         rv = ((Uit - uh) @ Rt).reshape(-1, 4).contiguous()
         qN = ((Xterm - ref[:, N]) @ Qt).contiguous()
-        ric = rtn.riccati(lin["A"], lin["B"], Q, R, Q, offsets=off, c=c, q=qv, r=rv, qN=qN)
         dx0 = (torch.from_numpy(xa).to(dev) - Xit[:, 0]).contiguous()
-        roll = rtn.lq_rollout(lin["A"], lin["B"], ric["K"], ric["kff"], dx0, offsets=off, c=c)
+        if box:
+            lo = (-Uit).reshape(-1, 4).contiguous()
+            hi = (U_MAX - Uit).reshape(-1, 4).contiguous()
+            roll = rtn.riccati_box(lin["A"], lin["B"], Q, R, Q, dx0, lo, hi, offsets=off, c=c, q=qv, r=rv, qN=qN,
+                                   rho=1.0, max_iter=200, tol=1e-6)
+        else:
+            ric = rtn.riccati(lin["A"], lin["B"], Q, R, Q, offsets=off, c=c, q=qv, r=rv, qN=qN)
+            roll = rtn.lq_rollout(lin["A"], lin["B"], ric["K"], ric["kff"], dx0, offsets=off, c=c)
         du = roll["du"].view(n_inst, N, 4)
         dx = roll["dx"].view(n_inst, N, 13)
         u0 = torch.clamp(Uit[:, 0] + du[:, 0], 0.0, U_MAX)

@@ -197,3 +197,19 @@ def test_closed_loop_rollouts_trained_vs_nominal(torch, trained):
     assert nom["finite"] and lrn["finite"]
     assert lrn["pred_err"] < 0.5 * nom["pred_err"]
     assert lrn["track_err"] < nom["track_err"]
+
+
+def test_closed_loop_with_input_box_trained_vs_nominal(torch, trained):
+    """The same rollouts with the input box inside the QP (rtn_riccati_box)."""
+    import paper_2203_07747_amd as rtn
+    from closed_loop import run
+    m, _, _ = trained
+    print("[gpu] closed loop with input box, nominal", flush=True)
+    nom = run(torch, rtn, None, "fp32", box=True)
+    print(f"  nominal: {nom}", flush=True)
+    print("[gpu] closed loop with input box, trained", flush=True)
+    lrn = run(torch, rtn, m, "bf16", box=True)
+    print(f"  trained: {lrn}", flush=True)
+    assert nom["finite"] and lrn["finite"]
+    assert lrn["pred_err"] < 0.5 * nom["pred_err"]
+    assert lrn["track_err"] < nom["track_err"]

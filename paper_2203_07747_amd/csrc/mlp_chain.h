@@ -99,11 +99,16 @@ hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const
                           const float* A, const float* B, const double* c, const double* q, const double* r,
                           const double* qN, double* K, double* kff, double* P, hipStream_t st);
 
-hipError_t launch_gemm_strided(int prec, int M, int N, int K, const float* A, long sAm, long sAk, const float* B,
-                               long sBk, long sBn, float* C, long sCm, int accumulate, const void* gate,
-                               int gate_is_f32, int ldg, hipStream_t st);
+// C (+)= A B for A(m,k) = A[m*sAm + k*sAk], B(k,n) = B[k*sBk + n*sBn], C row stride
+// sCm; Cone (nullable) (+)= the product with an all-ones column of B (column sums
+// of A); gate (nullable): result *= act'(m, n) from a stash [M][ldg] in stash
+// order; part (nullable): split-K scratch of gemm_part_floats(M, N, K) floats.
+hipError_t launch_gemm(int prec, int M, int N, int K, const float* A, long sAm, long sAk, const float* B, long sBk,
+                       long sBn, float* C, long sCm, float* Cone, int accumulate, const void* gate, int gate_is_f32,
+                       int ldg, float* part, hipStream_t st);
+int gemm_splits(int M, int N, int K);
+inline long gemm_part_floats(int M, int N, int K) { return (long)gemm_splits(M, N, K) * M * (N + 1); }
 hipError_t launch_mse(int nel, const float* y, const float* t, float* dy, float* loss, hipStream_t st);
-hipError_t launch_colsum(int rows, int cols, const float* d, float* db, hipStream_t st);
 hipError_t launch_adam(long n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                        float bc1, float bc2, hipStream_t st);
 

@@ -28,6 +28,9 @@ struct Model {
   float* scales = nullptr;
   float* w_out_s = nullptr;  // W_{L+1} with each row in stash order
   bool calibrated = false;
+  // packed copies are refreshed lazily, per precision, after the master weights change
+  bool pack_ok[3] = {false, false, false};
+  bool wout_ok = false;
   // workspace (grown on demand)
   void* stash = nullptr;
   size_t stash_bytes = 0;
@@ -40,6 +43,7 @@ struct Model {
   float* ty = nullptr;
   float* tdy = nullptr;
   float* tdelta[2] = {nullptr, nullptr};
+  float* tpart = nullptr;  // split-K partial tiles of the backward products
   const float* tin = nullptr;
   int64_t tcap = 0;
   int32_t tbatch = 0, tprec = -1;
@@ -63,7 +67,9 @@ struct Model {
   rtn_status init(const rtn_mlp_desc& d);
   rtn_status alloc(void** p, size_t bytes);
   void release(void* p);
-  rtn_status repack(hipStream_t st);
+  rtn_status repack(hipStream_t st);  // mark every packed copy stale and refresh all three
+  void invalidate_packs() { pack_ok[0] = pack_ok[1] = pack_ok[2] = wout_ok = false; }
+  rtn_status ensure_packed(int prec, hipStream_t st);
   rtn_status ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st);
   NetView view(int prec) const;
   LatNet lat_view() const;

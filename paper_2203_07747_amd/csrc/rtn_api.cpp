@@ -1,6 +1,7 @@
 // C ABI of the library: argument validation, model ownership and dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdarg>
@@ -161,21 +162,36 @@ NetView rtn::Model::view(int prec) const {
   return v;
 }
 
-// Refresh packed copies of the fp32 master weights (and the fp8 weight scales).
-rtn_status rtn::Model::repack(hipStream_t st) {
-  for (int l = 0; l <= L; ++l) {
-    int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
-    HIP_TRY(hipMemsetAsync(scales + l, 0, 4, st));
-    HIP_TRY(launch_amax(params + w_off[l], (long)fo * fi, scales + l, st));
+// Refresh the packed copy of one precision (and, for fp8, the weight scales)
+// from the fp32 master weights if they changed since it was made.
+rtn_status rtn::Model::ensure_packed(int prec, hipStream_t st) {
+  if (!wout_ok) {
+    HIP_TRY(launch_reorder_out(params + w_off[L], H, w_out_s, st));
+    wout_ok = true;
   }
-  HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
-  HIP_TRY(launch_reorder_out(params + w_off[L], H, w_out_s, st));
-  for (int p = 0; p < 3; ++p) {
+  if (pack_ok[prec]) return RTN_OK;
+  if (prec == P_FP8) {
     for (int l = 0; l <= L; ++l) {
       int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
-      HIP_TRY(launch_pack(p, params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[p][l], st));
-      if (l < L) HIP_TRY(launch_pack(p, params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[p][l], st));
+      HIP_TRY(hipMemsetAsync(scales + l, 0, 4, st));
+      HIP_TRY(launch_amax(params + w_off[l], (long)fo * fi, scales + l, st));
     }
+    HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
+  }
+  for (int l = 0; l <= L; ++l) {
+    int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
+    HIP_TRY(launch_pack(prec, params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[prec][l], st));
+    if (l < L) HIP_TRY(launch_pack(prec, params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[prec][l], st));
+  }
+  pack_ok[prec] = true;
+  return RTN_OK;
+}
+
+rtn_status rtn::Model::repack(hipStream_t st) {
+  invalidate_packs();
+  for (int p = 0; p < 3; ++p) {
+    rtn_status s = ensure_packed(p, st);
+    if (s) return s;
   }
   return RTN_OK;
 }
@@ -322,6 +338,7 @@ rtn_status rtn_model_calibrate(rtn_model* model, int32_t n, const float* x, cons
   float* a_amax = m->scales + (L + 1);
   float* g_amax = m->scales + 2 * (L + 1);
   HIP_TRY(hipMemsetAsync(a_amax, 0, (2 * L + 1) * 4, st));
+  if ((s = m->ensure_packed(P_FP32, st))) return s;
   NetView v = m->view(P_FP32);
   float* y = m->tmp;
   float* J = m->tmp + (size_t)n * kDout;
@@ -338,6 +355,8 @@ rtn_status rtn_model_get_scales(const rtn_model* model, float* scales_host, int3
   const Model* m = reinterpret_cast<const Model*>(model);
   if (n_scales) *n_scales = 3 * m->L + 2;
   if (scales_host) {
+    rtn_status s = const_cast<Model*>(m)->ensure_packed(P_FP8, nullptr);  // current weight scales
+    if (s) return s;
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(scales_host, m->scales, (3 * m->L + 2) * 4, hipMemcpyDeviceToHost));
     if (!m->calibrated)
@@ -396,6 +415,7 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
   if ((s = m->ensure_workspace(n_nodes, 0, st))) return s;
   float* y = f_D ? f_D : m->tmp;
   float* J = J_D ? J_D : m->tmp + (size_t)n_nodes * kDout;
+  if (rtn_status sp = m->ensure_packed(prec, st)) return sp;
   const NetView v = m->view(prec);
   // tile shapes and workgroup counts: the tuned choice for this size class,
   // timed here on first use unless tuning is off or the stream is being captured
@@ -718,10 +738,10 @@ extern "C" rtn_status rtn_tune_load(const char* path) {
 rtn_status rtn::Model::ensure_train_workspace(int64_t batch, hipStream_t st) {
   if (batch <= tcap) return RTN_OK;
   HIP_TRY(hipStreamSynchronize(st));
-  void* old[] = {tstash, hsave, ty, tdy, tdelta[0], tdelta[1]};
+  void* old[] = {tstash, hsave, ty, tdy, tdelta[0], tdelta[1], tpart};
   for (void* p : old) release(p);
   tstash = nullptr;
-  hsave = ty = tdy = tdelta[0] = tdelta[1] = nullptr;
+  hsave = ty = tdy = tdelta[0] = tdelta[1] = tpart = nullptr;
   tcap = 0;
   rtn_status s;
   if ((s = alloc(&tstash, (size_t)L * batch * H * 4))) return s;
@@ -730,6 +750,15 @@ rtn_status rtn::Model::ensure_train_workspace(int64_t batch, hipStream_t st) {
   if ((s = alloc((void**)&tdy, (size_t)batch * kDout * 4))) return s;
   for (int i = 0; i < 2; ++i)
     if ((s = alloc((void**)&tdelta[i], (size_t)batch * H * 4))) return s;
+  // split-K partial tiles: the largest over the backward products
+  long part = gemm_part_floats(kDout, H, (int)batch);
+  for (int l = 0; l < L; ++l) {
+    const int fi = l == 0 ? kDin : H;
+    part = std::max(part, gemm_part_floats(H, fi, (int)batch));
+    part = std::max(part, gemm_part_floats((int)batch, l == 0 ? kDin : H, H));
+  }
+  part = std::max(part, gemm_part_floats((int)batch, H, kDout));
+  if ((s = alloc((void**)&tpart, (size_t)part * 4))) return s;
   tcap = batch;
   return RTN_OK;
 }
@@ -737,6 +766,7 @@ rtn_status rtn::Model::ensure_train_workspace(int64_t batch, hipStream_t st) {
 static rtn_status train_forward(Model* m, int32_t prec, int32_t batch, const float* in, hipStream_t st) {
   rtn_status s = m->ensure_train_workspace(batch, st);
   if (s) return s;
+  if (rtn_status sp = m->ensure_packed(prec, st)) return sp;
   NetView v = m->view(prec);
   ProfScope ps("mlp_forward_chain(train)", st);
   HIP_TRY(launch_mlp_forward(prec, m->H, v, batch, nullptr, nullptr, in, m->tstash, m->ty, nullptr, st, m->hsave));
@@ -753,26 +783,26 @@ static rtn_status train_backward(Model* m, const float* dy, float* din, hipStrea
   const size_t sb = (size_t)(prec == P_FP32 ? 4 : 2);
   const char* stash = static_cast<const char*>(m->tstash);
   ProfScope ps("train_backward", st);
+  float* part = m->tpart;
   // output layer W_{L+1} (6 x H): dW = dy^T h_L, db = sum dy, delta_L = (dy W) * act'(a_L)
-  HIP_TRY(launch_gemm_strided(prec, kDout, H, B, dy, 1, kDout, m->hsave + (size_t)(L - 1) * B * H, H, 1,
-                              m->grad + m->w_off[L], H, 1, nullptr, 1, 0, st));
-  HIP_TRY(launch_colsum(B, kDout, dy, m->grad + m->b_off[L], st));
-  HIP_TRY(launch_gemm_strided(prec, B, H, kDout, dy, kDout, 1, m->params + m->w_off[L], H, 1, m->tdelta[0], H, 0,
-                              stash + (size_t)(L - 1) * B * H * sb, gate_f32, H, st));
+  HIP_TRY(launch_gemm(prec, kDout, H, B, dy, 1, kDout, m->hsave + (size_t)(L - 1) * B * H, H, 1,
+                      m->grad + m->w_off[L], H, m->grad + m->b_off[L], 1, nullptr, 1, 0, part, st));
+  HIP_TRY(launch_gemm(prec, B, H, kDout, dy, kDout, 1, m->params + m->w_off[L], H, 1, m->tdelta[0], H, nullptr, 0,
+                      stash + (size_t)(L - 1) * B * H * sb, gate_f32, H, part, st));
   int cur = 0;
   for (int l = L - 1; l >= 0; --l) {  // weight W_{l+1}: fan_out H, fan_in (l == 0 ? 14 : H)
     const int fi = l == 0 ? kDin : H;
     const float* hin = l == 0 ? m->tin : m->hsave + (size_t)(l - 1) * B * H;
     const float* d = m->tdelta[cur];
-    HIP_TRY(launch_gemm_strided(prec, H, fi, B, d, 1, H, hin, fi, 1, m->grad + m->w_off[l], fi, 1, nullptr, 1, 0, st));
-    HIP_TRY(launch_colsum(B, H, d, m->grad + m->b_off[l], st));
+    HIP_TRY(launch_gemm(prec, H, fi, B, d, 1, H, hin, fi, 1, m->grad + m->w_off[l], fi, m->grad + m->b_off[l], 1,
+                        nullptr, 1, 0, part, st));
     if (l > 0) {
-      HIP_TRY(launch_gemm_strided(prec, B, H, H, d, H, 1, m->params + m->w_off[l], H, 1, m->tdelta[cur ^ 1], H, 0,
-                                  stash + (size_t)(l - 1) * B * H * sb, gate_f32, H, st));
+      HIP_TRY(launch_gemm(prec, B, H, H, d, H, 1, m->params + m->w_off[l], H, 1, m->tdelta[cur ^ 1], H, nullptr, 0,
+                          stash + (size_t)(l - 1) * B * H * sb, gate_f32, H, part, st));
       cur ^= 1;
     } else if (din) {
-      HIP_TRY(launch_gemm_strided(prec, B, kDin, H, d, H, 1, m->params + m->w_off[0], kDin, 1, din, kDin, 0, nullptr,
-                                  1, 0, st));
+      HIP_TRY(launch_gemm(prec, B, kDin, H, d, H, 1, m->params + m->w_off[0], kDin, 1, din, kDin, nullptr, 0, nullptr,
+                          1, 0, part, st));
     }
   }
   return RTN_OK;
@@ -787,7 +817,8 @@ static rtn_status adam_update(Model* m, float lr, float b1, float b2, float eps,
     ProfScope ps("adam", st);
     HIP_TRY(launch_adam(m->n_params, m->params, m->grad, m->adam_m, m->adam_v, lr, b1, b2, eps, bc1, bc2, st));
   }
-  return m->repack(st);
+  m->invalidate_packs();  // packed copies are refreshed by the next call that needs one
+  return RTN_OK;
 }
 
 static rtn_status check_train_prec(int32_t prec) {
@@ -920,6 +951,7 @@ extern "C" rtn_status rtn_linearize_exact(const rtn_model* model, int32_t prec, 
   float* y = m->tmp;
   float* J = m->tmp + (size_t)n_nodes * kDout;
   QuadConst qc{quad->mass, quad->Jx, quad->Jy, quad->Jz, quad->arm, quad->c_tau, quad->g};
+  if (rtn_status sp = m->ensure_packed(prec, st)) return sp;
   const NetView v = m->view(prec);
   for (int stage = 0; stage < 4; ++stage) {
     const float* xin = stage == 0 ? x : xs;

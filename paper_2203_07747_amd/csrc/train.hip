@@ -4,9 +4,11 @@
 // hidden activation h_l.  Backward, layer by layer from the output:
 //   dW_l = delta_l^T h_{l-1},  db_l = sum_b delta_l,
 //   delta_{l-1} = (delta_l W_l) * act'(a_{l-1})          (act' from the stash)
-// with delta_{L+1} = dL/dy = 2 (y - y*) / (6 B).  The products are small GEMMs
-// (K = batch for dW) done by one LDS-tiled matrix-core kernel with strided
-// operands; the reductions are deterministic (fixed order).
+// with delta_{L+1} = dL/dy = 2 (y - y*) / (6 B).  The products are GEMMs with
+// strided operands on one LDS-tiled matrix-core kernel; dW and db come from one
+// product (db is the product with an extra all-ones column of h), split over
+// the batch into K ranges whose partial tiles are summed in fixed order, so the
+// result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -19,66 +21,141 @@ constexpr int TBM = 64, TBN = 64, TBK = 32;
 __device__ inline float from_bits(float v) { return v; }
 __device__ inline float from_bits(uint16_t v) { return bf16_to_f32(v); }
 
-// C[m][n] (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sAm + k*sAk], B(k,n) = B[k*sBk + n*sBn].
-// Optional gate: C[m][n] *= act'(row m, feature n) read from a stash [M][ldg] in
-// stash order.  One 64x64 output tile per workgroup, 4 waves of 32x32.
-template <int P, typename S>
-__global__ void __launch_bounds__(256)
-gemm_strided(int M, int N, int K, const float* __restrict__ A, long sAm, long sAk, const float* __restrict__ B,
-             long sBk, long sBn, float* __restrict__ C, long sCm, int accumulate, const S* __restrict__ gate,
-             int ldg) {
-  __shared__ float As[TBK][TBM + 1];
-  __shared__ float Bs[TBK][TBN + 1];
+// Operand element type staged in LDS: the MFMA input type.
+template <int P> struct GemmT { using T = float; };
+template <> struct GemmT<P_BF16> { using T = uint16_t; };
+__device__ inline void stage(float* d, float v) { *d = v; }
+__device__ inline void stage(uint16_t* d, float v) { *d = f32_to_bf16_rne(v); }
+
+struct GemmArgs {
+  int M, N, K;
+  const float* A;  // A(m, k) = A[m * sAm + k * sAk]
+  long sAm, sAk;
+  const float* B;  // B(k, n) = B[k * sBk + n * sBn]; with ones_col, B(k, N) = 1
+  long sBk, sBn;
+  float* C;        // C[m * sCm + n], n < N
+  long sCm;
+  float* Cone;     // nullable: C(m, N) of the ones column (a column sum of A)
+  int accumulate;  // C += result, else C = result
+  const void* gate;  // nullable: result *= act'(row m, feature n), stash [M][ldg] in stash order
+  int gate_f32, ldg;
+  float* part;     // split-K partial tiles [splits][M][N + 1] (splits > 1)
+  int kchunk;      // K range of one split
+};
+
+__device__ inline float gemm_epilogue(const GemmArgs& g, int m, int n, float v) {
+  if (g.gate && n < g.N) {
+    const long gi = (long)m * g.ldg + stash_pos(n);
+    v *= g.gate_f32 ? static_cast<const float*>(g.gate)[gi] : bf16_to_f32(static_cast<const uint16_t*>(g.gate)[gi]);
+  }
+  return v;
+}
+
+__device__ inline void gemm_store(const GemmArgs& g, int m, int n, float v) {
+  float* c = n < g.N ? g.C + (long)m * g.sCm + n : g.Cone + m;
+  *c = g.accumulate ? *c + v : v;
+}
+
+// C = A B (+ the ones column), one 64 x 64 output tile per workgroup and one K
+// range per grid z-slice; four waves of 32 x 32 (MFMA 32x32x16 bf16 or 32x32x2
+// fp32).  Operands are staged in LDS in the MFMA input type, k-contiguous per row
+// of the tile, loaded with 16-byte global reads along whichever dimension is
+// contiguous.  With one K range the epilogue is applied here, otherwise the fp32
+// partial tile is written for gemm_reduce.
+template <int P>
+__global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
+  using T = typename GemmT<P>::T;
+  constexpr int PAD = 16 / sizeof(T);  // 16-byte row padding against bank conflicts
+  __shared__ __attribute__((aligned(16))) T As[TBM][TBK + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[TBN][TBK + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+  const int NN = g.N + ones_col;
+  const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const bool a_vec_k = g.sAk == 1 && (g.sAm & 3) == 0 && ((uintptr_t)g.A & 15) == 0;
+  const bool a_vec_m = g.sAm == 1 && (g.sAk & 3) == 0 && ((uintptr_t)g.A & 15) == 0;
+  const bool b_vec_k = g.sBk == 1 && (g.sBn & 3) == 0 && ((uintptr_t)g.B & 15) == 0;
+  const bool b_vec_n = g.sBn == 1 && (g.sBk & 3) == 0 && ((uintptr_t)g.B & 15) == 0;
+  auto a_at = [&](int m, int k) -> float { return (m < g.M && k < ke) ? g.A[(long)m * g.sAm + (long)k * g.sAk] : 0.f; };
+  auto b_at = [&](int k, int n) -> float {
+    if (k >= ke || n >= NN) return 0.f;
+    return n < g.N ? g.B[(long)k * g.sBk + (long)n * g.sBn] : 1.f;
+  };
   f32x16 acc = {};
-  for (int k0 = 0; k0 < K; k0 += TBK) {
-    for (int e = tid; e < TBK * TBM; e += 256) {
-      // consecutive threads walk the operand's contiguous dimension
-      int kk, mm;
-      if (sAk == 1) { kk = e % TBK; mm = e / TBK; } else { mm = e % TBM; kk = e / TBM; }
-      const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? A[(long)m * sAm + (long)k * sAk] : 0.f;
+  for (int k0 = kb; k0 < ke; k0 += TBK) {
+    // A tile: 64 x 32 = 512 groups of 4
+    for (int e = tid; e < TBM * TBK / 4; e += 256) {
+      if (a_vec_k) {
+        const int mm = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
+        const int m = m0 + mm, k = k0 + kk;
+        float4 v;
+        if (m < g.M && k + 3 < ke) v = *reinterpret_cast<const float4*>(g.A + (long)m * g.sAm + k);
+        else v = make_float4(a_at(m, k), a_at(m, k + 1), a_at(m, k + 2), a_at(m, k + 3));
+        stage(&As[mm][kk], v.x); stage(&As[mm][kk + 1], v.y); stage(&As[mm][kk + 2], v.z); stage(&As[mm][kk + 3], v.w);
+      } else {
+        const int kk = e / (TBM / 4), mm = (e % (TBM / 4)) * 4;
+        const int m = m0 + mm, k = k0 + kk;
+        float4 v;
+        if (a_vec_m && m + 3 < g.M && k < ke) v = *reinterpret_cast<const float4*>(g.A + m + (long)k * g.sAk);
+        else v = make_float4(a_at(m, k), a_at(m + 1, k), a_at(m + 2, k), a_at(m + 3, k));
+        stage(&As[mm][kk], v.x); stage(&As[mm + 1][kk], v.y); stage(&As[mm + 2][kk], v.z); stage(&As[mm + 3][kk], v.w);
+      }
     }
-    for (int e = tid; e < TBK * TBN; e += 256) {
-      int kk, nn;
-      if (sBn == 1) { nn = e % TBN; kk = e / TBN; } else { kk = e % TBK; nn = e / TBK; }
-      const int n = n0 + nn, k = k0 + kk;
-      Bs[kk][nn] = (n < N && k < K) ? B[(long)k * sBk + (long)n * sBn] : 0.f;
+    // B tile: 32 x 64
+    for (int e = tid; e < TBN * TBK / 4; e += 256) {
+      if (b_vec_k) {
+        const int nn = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
+        const int n = n0 + nn, k = k0 + kk;
+        float4 v;
+        if (n < g.N && k + 3 < ke) v = *reinterpret_cast<const float4*>(g.B + k + (long)n * g.sBn);
+        else v = make_float4(b_at(k, n), b_at(k + 1, n), b_at(k + 2, n), b_at(k + 3, n));
+        stage(&Bs[nn][kk], v.x); stage(&Bs[nn][kk + 1], v.y); stage(&Bs[nn][kk + 2], v.z); stage(&Bs[nn][kk + 3], v.w);
+      } else {
+        const int kk = e / (TBN / 4), nn = (e % (TBN / 4)) * 4;
+        const int n = n0 + nn, k = k0 + kk;
+        float4 v;
+        if (b_vec_n && n + 3 < g.N && k < ke) v = *reinterpret_cast<const float4*>(g.B + (long)k * g.sBk + n);
+        else v = make_float4(b_at(k, n), b_at(k, n + 1), b_at(k, n + 2), b_at(k, n + 3));
+        stage(&Bs[nn][kk], v.x); stage(&Bs[nn + 1][kk], v.y); stage(&Bs[nn + 2][kk], v.z); stage(&Bs[nn + 3][kk], v.w);
+      }
     }
     __syncthreads();
+    const int r = lane & 31, h = lane >> 5;
     if constexpr (P == P_BF16) {
 #pragma unroll
       for (int ks = 0; ks < TBK; ks += 16) {
-        bf16x8 a, b;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          a[j] = (__bf16)As[ks + (lane >> 5) * 8 + j][wm + (lane & 31)];
-          b[j] = (__bf16)Bs[ks + (lane >> 5) * 8 + j][wn + (lane & 31)];
-        }
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + r][ks + h * 8]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + r][ks + h * 8]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
     } else {
 #pragma unroll
-      for (int ks = 0; ks < TBK; ks += 2) {
-        const float a = As[ks + (lane >> 5)][wm + (lane & 31)];
-        const float b = Bs[ks + (lane >> 5)][wn + (lane & 31)];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-      }
+      for (int ks = 0; ks < TBK; ks += 2)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[wm + r][ks + h], Bs[wn + r][ks + h], acc, 0, 0, 0);
     }
     __syncthreads();
   }
+  // accumulator register i of lane l: row (i/4)*8 + (l/32)*4 + i%4, column l%32
   const int n = n0 + wn + (lane & 31);
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int m = m0 + wm + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
-    if (m < M && n < N) {
-      float v = acc[i];
-      if (gate) v *= from_bits(gate[(long)m * ldg + stash_pos(n)]);
-      float* c = C + (long)m * sCm + n;
-      *c = accumulate ? *c + v : v;
-    }
+    if (m >= g.M || n >= NN) continue;
+    if (gridDim.z == 1) gemm_store(g, m, n, gemm_epilogue(g, m, n, acc[i]));
+    else g.part[((long)blockIdx.z * g.M + m) * (g.N + 1) + n] = acc[i];
+  }
+}
+
+// Sum of the split-K partial tiles in split order, then the epilogue.
+__global__ void gemm_reduce(GemmArgs g, int ones_col, int splits) {
+  const int NN = g.N + ones_col;
+  const long total = (long)g.M * NN;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int m = (int)(i / NN), n = (int)(i % NN);
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += g.part[((long)z * g.M + m) * (g.N + 1) + n];
+    gemm_store(g, m, n, gemm_epilogue(g, m, n, v));
   }
 }
 
@@ -103,15 +180,6 @@ __global__ void __launch_bounds__(1024) mse_kernel(int nel, const float* __restr
   if (threadIdx.x == 0 && loss) *loss = red[0] / (float)nel;
 }
 
-// db[o] (+)= sum_b delta[b][o], column sums in fixed order (one thread per column).
-__global__ void colsum_kernel(int rows, int cols, const float* __restrict__ d, float* __restrict__ db) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= cols) return;
-  float s = 0.f;
-  for (int b = 0; b < rows; ++b) s += d[(long)b * cols + o];
-  db[o] += s;
-}
-
 // Adam with bias correction (bc1 = 1 - beta1^t, bc2 = 1 - beta2^t), no weight decay.
 __global__ void adam_kernel(long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                             float* __restrict__ v, float lr, float b1, float b2, float eps, float bc1, float bc2) {
@@ -125,36 +193,41 @@ __global__ void adam_kernel(long n, float* __restrict__ p, const float* __restri
   }
 }
 
-hipError_t launch_gemm_strided(int prec, int M, int N, int K, const float* A, long sAm, long sAk, const float* B,
-                               long sBk, long sBn, float* C, long sCm, int accumulate, const void* gate,
-                               int gate_is_f32, int ldg, hipStream_t st) {
-  dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
-  if (grid.x == 0 || grid.y == 0) return hipSuccess;
-  if (prec == P_FP32) {
-    if (gate_is_f32 || !gate)
-      gemm_strided<P_FP32, float><<<grid, 256, 0, st>>>(M, N, K, A, sAm, sAk, B, sBk, sBn, C, sCm, accumulate,
-                                                        (const float*)gate, ldg);
-    else
-      gemm_strided<P_FP32, uint16_t><<<grid, 256, 0, st>>>(M, N, K, A, sAm, sAk, B, sBk, sBn, C, sCm, accumulate,
-                                                           (const uint16_t*)gate, ldg);
-  } else {
-    if (gate_is_f32 || !gate)
-      gemm_strided<P_BF16, float><<<grid, 256, 0, st>>>(M, N, K, A, sAm, sAk, B, sBk, sBn, C, sCm, accumulate,
-                                                        (const float*)gate, ldg);
-    else
-      gemm_strided<P_BF16, uint16_t><<<grid, 256, 0, st>>>(M, N, K, A, sAm, sAk, B, sBk, sBn, C, sCm, accumulate,
-                                                           (const uint16_t*)gate, ldg);
-  }
+// Split-K factor for an M x N (+1) output with reduction length K: enough
+// workgroups to cover the chip, K ranges of at least 256.
+int gemm_splits(int M, int N, int K) {
+  const long tiles = (long)((M + TBM - 1) / TBM) * ((N + 1 + TBN - 1) / TBN);
+  long s = (2L * num_cu() + tiles - 1) / tiles;
+  const long smax = K / 256 > 0 ? K / 256 : 1;
+  if (s > smax) s = smax;
+  if (s > 64) s = 64;
+  return s < 1 ? 1 : (int)s;
+}
+
+hipError_t launch_gemm(int prec, int M, int N, int K, const float* A, long sAm, long sAk, const float* B, long sBk,
+                       long sBn, float* C, long sCm, float* Cone, int accumulate, const void* gate, int gate_is_f32,
+                       int ldg, float* part, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int ones = Cone ? 1 : 0;
+  const int splits = (part && K > 0) ? gemm_splits(M, N, K) : 1;
+  GemmArgs g{M, N, K, A, sAm, sAk, B, sBk, sBn, C, sCm, Cone, accumulate, gate, gate_is_f32, ldg, part, 0};
+  g.kchunk = K > 0 ? (K + splits - 1) / splits : TBK;
+  g.kchunk = (g.kchunk + TBK - 1) / TBK * TBK;
+  const int splits_used = K > 0 ? (K + g.kchunk - 1) / g.kchunk : 1;
+  dim3 grid((N + ones + TBN - 1) / TBN, (M + TBM - 1) / TBM, splits_used);
+  if (prec == P_FP32) gemm_mfma<P_FP32><<<grid, 256, 0, st>>>(g, ones);
+  else gemm_mfma<P_BF16><<<grid, 256, 0, st>>>(g, ones);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits_used == 1) return e;
+  const long total = (long)M * (N + ones);
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  gemm_reduce<<<blocks, 256, 0, st>>>(g, ones, splits_used);
   return hipGetLastError();
 }
 
 hipError_t launch_mse(int nel, const float* y, const float* t, float* dy, float* loss, hipStream_t st) {
   mse_kernel<<<1, 1024, 0, st>>>(nel, y, t, dy, loss);
-  return hipGetLastError();
-}
-
-hipError_t launch_colsum(int rows, int cols, const float* d, float* db, hipStream_t st) {
-  colsum_kernel<<<(cols + 255) / 256, 256, 0, st>>>(rows, cols, d, db);
   return hipGetLastError();
 }
 

@@ -553,31 +553,47 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     {
       const float inv = P == P_FP8 ? 1.f / net.gscale[L - 1] : 1.f;
       float lmax = 0.f;
-      // unrolled to overlap the LDS reads of consecutive items, as far as the
-      // registers of the (E-wide) slot arrays allow
-      constexpr int PU = C::E >= 32 ? 1 : 4;
-#pragma unroll PU
-      for (int it = tid; it < C::RT * C::KS_H * kWave; it += NT) {
-        const int l = it % kWave, s = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
-        const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
-        const bool live = row < nrows;
-        const int node = live ? row / 6 : node0, j6 = live ? row - 6 * node : 0;
-        float v[C::E];
+      // Every thread handles ITEMS (row tile, K-step, lane) items; they are taken
+      // in groups of GI whose reads are all issued before any is used, so the
+      // read latency is paid once per group.  Rows past the end read node0 / row 0
+      // (valid addresses) and are zeroed by a mask, so no read is predicated.
+      constexpr int TOTAL = C::RT * C::KS_H * kWave;
+      static_assert(TOTAL % NT == 0, "operand items must split evenly over the threads");
+      constexpr int ITEMS = TOTAL / NT;
+      constexpr int GI = C::E >= 32 ? 1 : (ITEMS % 4 == 0 ? 4 : (ITEMS % 2 == 0 ? 2 : 1));
+#pragma unroll 1
+      for (int i0 = 0; i0 < ITEMS; i0 += GI) {
+        float spv[GI][C::E], wv[GI][C::E], msk[GI];
+        int rts[GI], ss[GI];
 #pragma unroll
-        for (int run = 0; run < C::E / RL; ++run) {
-          const int q0 = s * C::E + run * RL;
-          const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
-          float spv[RL], wv[RL];
-          load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, spv);
-          load_run<RL>(wo + j6 * wo_stride + pos, wv);
+        for (int gi = 0; gi < GI; ++gi) {
+          const int it = tid + (i0 + gi) * NT;
+          const int l = it % kWave, sk = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
+          const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
+          const bool live = row < nrows;
+          const int node = live ? row / 6 : node0, j6 = live ? row - 6 * node : 0;
+          msk[gi] = live ? 1.f : 0.f;
+          rts[gi] = rt;
+          ss[gi] = sk;
 #pragma unroll
-          for (int t = 0; t < RL; ++t) v[run * RL + t] = live ? wv[t] * spv[t] : 0.f;
+          for (int run = 0; run < C::E / RL; ++run) {
+            const int q0 = sk * C::E + run * RL;
+            const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
+            load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, spv[gi] + run * RL);
+            load_run<RL>(wo + j6 * wo_stride + pos, wv[gi] + run * RL);
+          }
         }
-        if (amax) {
 #pragma unroll
-          for (int j = 0; j < C::E; ++j) lmax = fmaxf(lmax, fabsf(v[j]));
+        for (int gi = 0; gi < GI; ++gi) {
+          float v[C::E];
+#pragma unroll
+          for (int t = 0; t < C::E; ++t) v[t] = wv[gi][t] * spv[gi][t] * msk[gi];
+          if (amax) {
+#pragma unroll
+            for (int j = 0; j < C::E; ++j) lmax = fmaxf(lmax, fabsf(v[j]));
+          }
+          C::put_slots(lds, rts[gi], ss[gi], tid % kWave, C::KS_H, v, inv);
         }
-        C::put_slots(lds, rt, s, l, C::KS_H, v, inv);
       }
       if (amax) atomic_amax(&amax[L - 1], lmax);
     }

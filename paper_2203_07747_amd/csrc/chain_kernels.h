@@ -115,8 +115,21 @@ template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain
   // LDS element index of (row tile, K-step, lane, slot-in-step) for an operand with KS K-steps.
   __device__ static inline int lidx(int rt, int s, int lane, int KS) { return ((rt * KS + s) * kWave + lane) * E; }
 
+  // fp8: the 32 bytes of a lane's fragment are two 16-byte halves kept in separate
+  // planes of the K-step's block, so every 16-byte LDS access of a wave has a
+  // 16-byte lane stride (a 32-byte stride puts two lanes on each bank group)
+  __device__ static inline int hidx(int rt, int s, int half, int lane, int KS) {
+    return (((rt * KS + s) * 2 + half) * kWave + lane) * 16;
+  }
+
   __device__ static inline frag lds_frag(const elem* lds, int rt, int s, int lane, int KS) {
-    return *reinterpret_cast<const frag*>(lds + lidx(rt, s, lane, KS));
+    if constexpr (P == P_FP8) {
+      const i32x4 lo = *reinterpret_cast<const i32x4*>(lds + hidx(rt, s, 0, lane, KS));
+      const i32x4 hi = *reinterpret_cast<const i32x4*>(lds + hidx(rt, s, 1, lane, KS));
+      return frag{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    } else {
+      return *reinterpret_cast<const frag*>(lds + lidx(rt, s, lane, KS));
+    }
   }
 
   // acc[i][r] = sum over NSTEPS K-steps from s0 of A(mt0+i, s) * B(r, s), NMT M-tiles.
@@ -249,7 +262,7 @@ template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain
       for (int j = 0; j < 4; ++j)
         w[j] = (int)(f32x2_to_e4m3(v[4 * j] * inv_scale, v[4 * j + 1] * inv_scale) |
                      (f32x2_to_e4m3(v[4 * j + 2] * inv_scale, v[4 * j + 3] * inv_scale) << 16));
-      *reinterpret_cast<i32x4*>(lds + lidx(rt, mt >> 1, lane, KS_H) + (mt & 1) * 16) = w;
+      *reinterpret_cast<i32x4*>(lds + hidx(rt, mt >> 1, mt & 1, lane, KS_H)) = w;
     }
   }
 
@@ -290,7 +303,7 @@ template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain
         for (int j = 0; j < 4; ++j)
           w[j] = (int)(f32x2_to_e4m3(v[16 * h + 4 * j] * inv_scale, v[16 * h + 4 * j + 1] * inv_scale) |
                        (f32x2_to_e4m3(v[16 * h + 4 * j + 2] * inv_scale, v[16 * h + 4 * j + 3] * inv_scale) << 16));
-        *reinterpret_cast<i32x4*>(dst + 16 * h) = w;
+        *reinterpret_cast<i32x4*>(lds + hidx(rt, s, h, lane, KS)) = w;
       }
     }
   }

@@ -49,6 +49,12 @@ def silu_prime(a):
     return s * (1.0 + a * (1.0 - s))
 
 
+def silu_second(a):
+    """d^2/da^2 of a * logistic(a) = s (1 - s) (2 + a (1 - 2 s))."""
+    s = logistic(a)
+    return s * (1.0 - s) * (2.0 + a * (1.0 - 2.0 * s))
+
+
 class MLP:
     """Float64 view of a residual network.  ``Ws[l]`` is (fan_out, fan_in)."""
 
@@ -69,9 +75,14 @@ class MLP:
     def _act_prime(self, a):
         return silu_prime(a) if self.act == "silu" else np.ones_like(a)
 
+    def _act_second(self, a):
+        return silu_second(a) if self.act == "silu" else np.zeros_like(a)
+
     def forward(self, z: np.ndarray, keep: bool = False):
-        """y (n, 6); with keep=True also the pre-activations a_1..a_L."""
-        h = np.asarray(z, dtype=np.float64)
+        """y (n, 6); with keep=True also the pre-activations a_1..a_L.  Complex inputs
+        stay complex (complex-step differentiation in the tests)."""
+        z = np.asarray(z)
+        h = np.asarray(z, dtype=np.result_type(z, 1.0))
         pre = []
         for W, b in zip(self.Ws[:-1], self.bs[:-1]):
             a = h @ W.T + b
@@ -88,6 +99,29 @@ class MLP:
         for l in range(self.n_hidden - 1, -1, -1):
             G = (G * self._act_prime(pre[l])[:, None, :]) @ self.Ws[l]
         return y, np.ascontiguousarray(G)
+
+
+    def hessian(self, z: np.ndarray):
+        """(y (n,6), J_D (n,6,14), H_D (n,6,14,14)): the second derivatives of the outputs
+        w.r.t. z_0 by the chain rule of second order,
+
+            H_j = sum_l T_l^T diag((dy_j/dh_l) * act''(a_l)) T_l,   T_l = da_l/dz_0,
+
+        with T_1 = W_1, T_l = W_l diag(act'(a_{l-1})) T_{l-1} (tangents, forward) and
+        dy/dh_L = W_{L+1}, dy/dh_{l-1} = (dy/dh_l * act'(a_l)) W_l (adjoints, reverse);
+        the last adjoint is J_D."""
+        y, pre = self.forward(z, keep=True)
+        n, L = y.shape[0], self.n_hidden
+        T = [np.broadcast_to(self.Ws[0], (n,) + self.Ws[0].shape)]
+        for l in range(1, L):
+            T.append(np.einsum("fg,ngc->nfc", self.Ws[l], self._act_prime(pre[l - 1])[:, :, None] * T[l - 1]))
+        Hs = np.zeros((n, 6, z.shape[1], z.shape[1]), dtype=np.result_type(z, 1.0))
+        U = np.broadcast_to(self.Ws[-1], (n,) + self.Ws[-1].shape)  # dy/dh_L
+        for l in range(L - 1, -1, -1):
+            w = U * self._act_second(pre[l])[:, None, :]
+            Hs = Hs + np.einsum("nfc,njf,nfd->njcd", T[l], w, T[l])
+            U = (U * self._act_prime(pre[l])[:, None, :]) @ self.Ws[l]
+        return y, np.ascontiguousarray(U), Hs
 
 
 def residual_in_state(y: np.ndarray, J: np.ndarray):

@@ -150,3 +150,67 @@ def linearize_exact(x: np.ndarray, u: np.ndarray, model: Optional[MLP], dt: floa
     x_next = x + dt / 6.0 * x_acc
     AB = S0 + dt / 6.0 * S_acc
     return x_next, AB[:, :, :13], AB[:, :, 13:]
+
+
+# ---------------------------------------------------------------- second order
+# eq. (4) with its second-order term: the local approximation about the node is
+#     f_D**(x, u) = f_D-bar + J_D dz + 1/2 dz^T H_D dz,   dz = z_0(x, u) - z_0(x_k, u_k),
+# (per output; z_0 = [v, w, q, u] is a linear selection of (x, u)), again with
+# (x_k, u_k, f_D-bar, J_D, H_D) held fixed inside the RK4 step.  Its derivative
+# w.r.t. the state or input is (J_D + H_D dz) applied to d z_0.
+
+def quadratic_field(x_k, u_k, y_bar, J, H, quad: QuadParams = QUAD):
+    z_k = pack_input(x_k, u_k)
+
+    def F(x, u):
+        dz = pack_input(x, u) - z_k
+        y = y_bar + np.einsum("njc,nc->nj", J, dz) + 0.5 * np.einsum("nc,njcd,nd->nj", dz, H, dz)
+        out = nominal_f(x, u, quad).copy()
+        out[:, 7:13] += y
+        return out
+    return F
+
+
+def quadratic_phi(x0, u0, x_k, u_k, y_bar, J, H, dt: float, quad: QuadParams = QUAD) -> np.ndarray:
+    return rk4_step(quadratic_field(x_k, u_k, y_bar, J, H, quad), np.asarray(x0, np.float64),
+                    np.asarray(u0, np.float64), dt)
+
+
+def linearize_quadratic(x: np.ndarray, u: np.ndarray, model: Optional[MLP], dt: float,
+                        quad: QuadParams = QUAD, params=None):
+    """(x_next, A, B, f_D-bar, J_D, H_D): RK4 of f_F + f_D** and its exact derivative.
+    ``params`` = (f_D-bar, J_D, H_D) supplies the approximation's parameters directly."""
+    x = np.asarray(x, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    n = x.shape[0]
+    if params is None:
+        if model is None:
+            y_bar, J, H = np.zeros((n, 6)), np.zeros((n, 6, 14)), np.zeros((n, 6, 14, 14))
+        else:
+            y_bar, J, H = model.hessian(pack_input(x, u))
+    else:
+        y_bar, J, H = (np.asarray(a, dtype=np.float64) for a in params)
+    z_k = pack_input(x, u)
+    S0 = np.zeros((n, 13, 17))
+    S0[:, :, :13] = np.eye(13)
+    xs, S = x, S0
+    x_acc = np.zeros_like(x)
+    S_acc = np.zeros_like(S0)
+    for s in range(4):
+        if s > 0:
+            xs = x + RK4_C[s] * dt * k
+            S = S0 + RK4_C[s] * dt * dk
+        dz = pack_input(xs, u) - z_k
+        y = y_bar + np.einsum("njc,nc->nj", J, dz) + 0.5 * np.einsum("nc,njcd,nd->nj", dz, H, dz)
+        J_eff = J + np.einsum("njcd,nd->njc", H, dz)
+        _, J_x, J_u = residual_in_state(y, J_eff)
+        Fx, Fu = nominal_jac(xs, u, quad)
+        k = nominal_f(xs, u, quad).copy()
+        k[:, 7:13] += y
+        dk = (Fx + J_x) @ S
+        dk[:, :, 13:] += Fu + J_u
+        x_acc = x_acc + RK4_W[s] * k
+        S_acc = S_acc + RK4_W[s] * dk
+    x_next = x + dt / 6.0 * x_acc
+    AB = S0 + dt / 6.0 * S_acc
+    return x_next, AB[:, :, :13], AB[:, :, 13:], y_bar, J, H

@@ -453,3 +453,87 @@ def test_box_lq_kkt_conditions():
     assert np.all(g[at_lo] > -1e-9) and np.all(g[at_hi] < 1e-9)
     for k in range(N):
         np.testing.assert_allclose(dx[k + 1], A[k] @ dx[k] + B[k] @ du[k] + c[k], atol=1e-10)
+
+
+# ---------------------------------------------------------------- second-order approximation (eq. (4))
+
+def _hess_net(act="silu"):
+    Ws, bs = xavier_params(3, 32, seed=3)
+    bs = [np.random.default_rng(1).normal(size=b.shape) * 0.1 for b in bs]
+    return MLP(Ws, bs, act)
+
+
+def test_hessian_matches_complex_step_of_the_jacobian():
+    from oracle.mlp import pack_input as pk
+    net = _hess_net()
+    x, u = sample_nodes(6, seed=2)
+    z = pk(x, u)
+    _, J, H = net.hessian(z)
+    _, J_ref = net.jacobian(z)
+    np.testing.assert_array_equal(J, J_ref)
+    h = 1e-20
+    Hc = np.zeros_like(H)
+    for c in range(14):
+        zc = z.astype(complex)
+        zc[:, c] += 1j * h
+        Hc[:, :, :, c] = net.jacobian(zc)[1].imag / h
+    assert np.abs(H - Hc).max() < 1e-12 * np.abs(H).max()
+    np.testing.assert_allclose(H, H.transpose(0, 1, 3, 2), atol=1e-15)
+
+
+def test_hessian_of_a_linear_network_vanishes():
+    from oracle.mlp import pack_input as pk
+    net = _hess_net("identity")
+    x, u = sample_nodes(4, seed=3)
+    _, _, H = net.hessian(pk(x, u))
+    assert np.abs(H).max() == 0.0
+
+
+def test_quadratic_linearisation_matches_finite_differences():
+    from oracle.rk4 import linearize_quadratic, quadratic_phi
+    net = _hess_net()
+    x, u = sample_nodes(4, seed=4)
+    dt = 0.05
+    xq, A, B, yb, J, H = linearize_quadratic(x, u, net, dt)
+    eps = 1e-6
+    for j in range(13):
+        xp, xm = x.astype(float).copy(), x.astype(float).copy()
+        xp[:, j] += eps
+        xm[:, j] -= eps
+        fd = (quadratic_phi(xp, u, x, u, yb, J, H, dt) - quadratic_phi(xm, u, x, u, yb, J, H, dt)) / (2 * eps)
+        np.testing.assert_allclose(A[:, :, j], fd, atol=1e-7)
+    for j in range(4):
+        up, um = u.astype(float).copy(), u.astype(float).copy()
+        up[:, j] += eps
+        um[:, j] -= eps
+        fd = (quadratic_phi(x, up, x, u, yb, J, H, dt) - quadratic_phi(x, um, x, u, yb, J, H, dt)) / (2 * eps)
+        np.testing.assert_allclose(B[:, :, j], fd, atol=1e-7)
+
+
+def test_quadratic_with_zero_hessian_is_the_first_order_step():
+    from oracle.rk4 import linearize_quadratic
+    net = _hess_net("identity")
+    x, u = sample_nodes(5, seed=5)
+    q = linearize_quadratic(x, u, net, 0.05)
+    a = linearize_affine(x, u, net, 0.05)
+    for g, r in zip(q[:5], a):
+        np.testing.assert_allclose(g, r, atol=1e-13)
+
+
+def test_second_order_approximation_error_is_third_order():
+    """Sec. IV-A: the error of the second-order approximation is of third order in the
+    change between nodes: gap(x_{k+1}) ~ dt^4, gap(A, B) ~ dt^3 against the exact step."""
+    from oracle.rk4 import linearize_quadratic
+    net = _hess_net()
+    x, u = sample_nodes(5, seed=2)
+    dts = [0.04, 0.02, 0.01, 0.005]
+    ex, eA = [], []
+    for dt in dts:
+        xq, Aq, Bq = linearize_quadratic(x, u, net, dt)[:3]
+        xe, Ae, Be = linearize_exact(x, u, net, dt)[:3]
+        ex.append(np.abs(xq - xe).max())
+        eA.append(max(np.abs(Aq - Ae).max(), np.abs(Bq - Be).max()))
+    sx = np.polyfit(np.log(dts), np.log(ex), 1)[0]
+    sA = np.polyfit(np.log(dts), np.log(eA), 1)[0]
+    assert abs(sx - 4) < 0.35, sx
+    assert abs(sA - 3) < 0.5, sA

@@ -166,6 +166,20 @@ rtn_status rtn_linearize_exact(const rtn_model* model, int32_t prec, const rtn_q
                                const float* x, const float* u, float* x_next, float* A, float* B,
                                void* stream);
 
+/* The second-order local approximation of eq. (4): the network is replaced
+ * inside the RK4 step by f_D-bar + J_D dz + 1/2 dz^T H_D dz (per output;
+ * dz = z_0(x, u) - z_0(x_k, u_k), z_0 = [v, omega, q, u]) with (x_k, u_k,
+ * f_D-bar, J_D, H_D) held fixed; x_{k+1}, A_k, B_k are the RK4 step and its exact
+ * derivatives.  H_D (6 x 14 x 14 per node) is the network's Hessian by the chain
+ * rule of second order.  prec must be RTN_FP32 (RTN_ENOTSUP otherwise); model
+ * is required; arguments and layouts as rtn_linearize (no status output), plus
+ *   H_D  nullable device fp32 [n][6][14][14]: H_D[k][j][a][b] = d^2 y_j / dz_a dz_b.
+ * Nodes are processed in chunks of up to 4096 with stream-ordered scratch. */
+rtn_status rtn_linearize_second(const rtn_model* model, int32_t prec, const rtn_quad* quad, float dt,
+                                int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                                const float* x, const float* u, float* x_next, float* A, float* B,
+                                float* f_D, float* J_D, float* H_D, void* stream);
+
 /* Feedback phase: backward Riccati recursion of the LQ problem
  *   min sum_k 1/2 [dx;du]^T blkdiag(Q,R) [dx;du] + q_k^T dx + r_k^T du
  *       + 1/2 dx_N^T Q_N dx_N + qN^T dx_N

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "linearize", "linearize_exact", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -293,6 +293,38 @@ def linearize_exact(x, u, model: Model, prec: str = "fp32", dt: float = 0.05, qu
                                      _dev(out["A"], torch.float32, (n, 13, 13), "A"),
                                      _dev(out["B"], torch.float32, (n, 13, 4), "B"), _stream(stream)),
           "rtn_linearize_exact")
+    return out
+
+
+def linearize_second(x, u, model: Model, dt: float = 0.05, quad=None, offsets: Optional[np.ndarray] = None,
+                     want_hessian: bool = True, out: Optional[Dict[str, object]] = None,
+                     stream=None) -> Dict[str, object]:
+    """rtn_linearize_second (fp32): RK4 of f_F plus the second-order local approximation.
+    Returns x_next, A, B, f_D, J_D and optionally H_D [n,6,14,14]."""
+    torch = _torch()
+    from workload import QUAD
+    q = quad_struct(quad if quad is not None else QUAD)
+    n = x.shape[0]
+    out = {} if out is None else out
+    shapes = [("x_next", (n, 13)), ("A", (n, 13, 13)), ("B", (n, 13, 4)), ("f_D", (n, 6)), ("J_D", (n, 6, 14))]
+    if want_hessian:
+        shapes.append(("H_D", (n, 6, 14, 14)))
+    for name, shape in shapes:
+        if out.get(name) is None:
+            out[name] = torch.empty(shape, dtype=torch.float32, device=x.device)
+    if offsets is None:
+        n_inst, off_ptr = 1, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    f32 = torch.float32
+    check(load().rtn_linearize_second(model.handle, PREC["fp32"], ctypes.byref(q), ctypes.c_float(dt), n_inst,
+                                      off_ptr, n, _dev(x, f32, (n, 13), "x"), _dev(u, f32, (n, 4), "u"),
+                                      _dev(out["x_next"], f32, (n, 13), "x_next"), _dev(out["A"], f32, (n, 13, 13), "A"),
+                                      _dev(out["B"], f32, (n, 13, 4), "B"), _dev(out["f_D"], f32, (n, 6), "f_D"),
+                                      _dev(out["J_D"], f32, (n, 6, 14), "J_D"),
+                                      _dev(out["H_D"], f32, (n, 6, 14, 14), "H_D") if want_hessian else None,
+                                      _stream(stream)), "rtn_linearize_second")
     return out
 
 

@@ -51,6 +51,9 @@ SIGNATURES = {
     "rtn_riccati": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]),
+    "rtn_linearize_second": (c_int32, [c_void_p, c_int32, c_void_p, c_float, c_int32, c_void_p, c_int32, c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p]),
     "rtn_riccati_box": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   ctypes.c_double, c_int32, ctypes.c_double, c_void_p, c_void_p, c_void_p,

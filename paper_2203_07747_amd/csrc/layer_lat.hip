@@ -19,10 +19,14 @@
 
 namespace rtn {
 
-// A operand (rows x K): z_0 packed from x, u | a row-major buffer | G_L formed
-// from W_{L+1} and act'(a_L).  B operand: W [N][K] read transposed (forward) or
-// W [K][N] (reverse).  Epilogue: SiLU with derivative | bias | derivative gate | none.
-enum LatA { LA_Z0 = 0, LA_ACT = 1, LA_GOUT = 2 };
+// A operand (rows x K): z_0 packed from x, u | a row-major buffer | a shared
+// weight matrix gated per node, wsrc(r % rpn, k) * gate_a[r / rpn][k] (G_L =
+// W_{L+1} (.) act'(a_L) with 6 rows per node; the first tangent layer with 14) |
+// a row-major buffer gated per node, A[r][k] * gate_a[r / rpn][k] (tangents).
+// B operand: W [N][K] read transposed (forward) or W [K][N] (reverse).
+// Epilogue: SiLU with derivative (and second derivative) | bias | derivative
+// gate (and the ungated value) | none.
+enum LatA { LA_Z0 = 0, LA_ACT = 1, LA_GOUT = 2, LA_TGATE = 3 };
 enum LatB { LB_NT = 0, LB_NN = 1 };
 enum LatE { LE_SILU = 0, LE_BIAS = 1, LE_GATE = 2, LE_NONE = 3 };
 
@@ -30,13 +34,17 @@ struct LatArgs {
   int M, N, K;                 // rows, output columns, reduction length
   const float* x;              // LA_Z0: [n][13]
   const float* u;              // LA_Z0: [n][4]
-  const float* A;              // LA_ACT: [M][K]; LA_GOUT: act'(a_L) [M/6][K]
-  const float* wout;           // LA_GOUT: W_{L+1} [6][K]
+  const float* A;              // LA_ACT, LA_TGATE: [M][K]
+  const float* wsrc;           // LA_GOUT: element (j, k) at wsrc[j * wj + k * wk]
+  long wj, wk;
+  const float* gate_a;         // LA_GOUT, LA_TGATE: [M / rpn][K]
+  int rpn;                     // LA_GOUT, LA_TGATE: operand rows per node
   const float* W;              // LB_NT: [N][K]; LB_NN: [K][N]
   const float* bias;           // LE_SILU, LE_BIAS: [N]
   const float* gate;           // LE_GATE: act'(a) [M/6][N]
   float* out;                  // [M][N]
-  float* dout;                 // LE_SILU: act'(a) [M][N]
+  float* dout;                 // LE_SILU: act'(a) [M][N]; LE_GATE (nullable): the ungated value [M][N]
+  float* ddout;                // LE_SILU (nullable): act''(a) [M][N]
   int act;                     // LE_SILU: 0 SiLU, 1 identity
 };
 
@@ -50,8 +58,10 @@ __device__ inline float lat_a(const LatArgs& p, int akind, int r, int k) {
     return p.u[(size_t)r * kNu + (k - 10)];                 // u
   }
   if (akind == LA_ACT) return p.A[(size_t)r * p.K + k];
-  const int node = r / 6, j = r - 6 * node;
-  return p.wout[(size_t)j * p.K + k] * p.A[(size_t)node * p.K + k];
+  const int node = r / p.rpn, j = r - p.rpn * node;
+  const float g = p.gate_a[(size_t)node * p.K + k];
+  if (akind == LA_TGATE) return p.A[(size_t)r * p.K + k] * g;
+  return p.wsrc[(size_t)j * p.wj + (size_t)k * p.wk] * g;
 }
 
 __device__ inline float lat_b(const LatArgs& p, int bkind, int k, int c) {
@@ -100,14 +110,17 @@ __global__ void __launch_bounds__(kLatWaves * kWave) lat_layer(LatArgs p) {
         const float sg = 1.f / (1.f + __expf(-a));
         p.out[o] = a * sg;
         p.dout[o] = sg * (1.f + a * (1.f - sg));
+        if (p.ddout) p.ddout[o] = sg * (1.f - sg) * (2.f + a * (1.f - 2.f * sg));
       } else {
         p.out[o] = a;
         p.dout[o] = 1.f;
+        if (p.ddout) p.ddout[o] = 0.f;
       }
     } else if constexpr (EP == LE_BIAS) {
       p.out[o] = s + p.bias[col];
     } else if constexpr (EP == LE_GATE) {
       p.out[o] = s * p.gate[(size_t)(row / 6) * p.N + col];
+      if (p.dout) p.dout[o] = s;
     } else {
       p.out[o] = s;
     }
@@ -127,7 +140,7 @@ template <int AK, int BK, int EP> static hipError_t lat_launch(const LatArgs& p,
 }
 
 hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const float* u, float* act, float* sp, float* y,
-                              hipStream_t st) {
+                              hipStream_t st, float* spp) {
   const int H = net.H, L = net.L;
   hipError_t e;
   for (int l = 0; l < L; ++l) {
@@ -142,6 +155,7 @@ hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const fl
     p.bias = net.b[l];
     p.out = act + (size_t)(l & 1) * n * H;      // h_l
     p.dout = sp + (size_t)l * n * H;
+    p.ddout = spp ? spp + (size_t)l * n * H : nullptr;
     p.act = net.act;
     e = l == 0 ? lat_launch<LA_Z0, LB_NT, LE_SILU>(p, st) : lat_launch<LA_ACT, LB_NT, LE_SILU>(p, st);
     if (e != hipSuccess) return e;
@@ -157,7 +171,8 @@ hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const fl
   return lat_launch<LA_ACT, LB_NT, LE_BIAS>(p, st);
 }
 
-hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* g, float* J, hipStream_t st) {
+hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* g, float* J, hipStream_t st,
+                              float* adj) {
   const int H = net.H, L = net.L;
   const int M = 6 * n;
   hipError_t e;
@@ -170,9 +185,13 @@ hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* 
     p.W = net.W[l];  // [H][H], reduction over its rows
     p.gate = sp + (size_t)(l - 1) * n * H;
     p.out = g + (size_t)(l & 1) * M * H;
+    p.dout = adj ? adj + (size_t)(l - 1) * M * H : nullptr;  // dy/dh of layer l (1-based)
     if (l == L - 1) {
-      p.A = sp + (size_t)(L - 1) * n * H;
-      p.wout = net.W[L];
+      p.gate_a = sp + (size_t)(L - 1) * n * H;
+      p.wsrc = net.W[L];
+      p.wj = H;
+      p.wk = 1;
+      p.rpn = 6;
       e = lat_launch<LA_GOUT, LB_NN, LE_GATE>(p, st);
     } else {
       p.A = g + (size_t)((l + 1) & 1) * M * H;
@@ -187,12 +206,39 @@ hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* 
   p.W = net.W[0];  // [H][14]
   p.out = J;
   if (L == 1) {
-    p.A = sp;
-    p.wout = net.W[L];
+    p.gate_a = sp;
+    p.wsrc = net.W[L];
+    p.wj = H;
+    p.wk = 1;
+    p.rpn = 6;
     return lat_launch<LA_GOUT, LB_NN, LE_NONE>(p, st);
   }
   p.A = g + (size_t)(1 & 1) * M * H;
   return lat_launch<LA_ACT, LB_NN, LE_NONE>(p, st);
+}
+
+// Tangents T_l = d a_l / d z_0 (14 rows per node, row (node, c) holds column c of
+// T_l) for l = 2..L (1-based): T_2 = W_2 (act'(a_1) (.) W_1) with W_1 read as a
+// gated shared matrix, T_l = W_l (act'(a_{l-1}) (.) T_{l-1}).  tan [2][14n][H]
+// ping-pong: layer l (0-based, l >= 1) lands in tan + (l & 1) * 14 n H.
+hipError_t launch_lat_tangent(const LatNet& net, int n, int l, const float* sp, float* tan, hipStream_t st) {
+  const int H = net.H;
+  LatArgs p{};
+  p.M = 14 * n;
+  p.N = H;
+  p.K = H;
+  p.W = net.W[l];
+  p.gate_a = sp + (size_t)(l - 1) * n * H;
+  p.rpn = 14;
+  p.out = tan + (size_t)(l & 1) * 14 * n * H;
+  if (l == 1) {
+    p.wsrc = net.W[0];  // W_1 [H][14]: element (c, g) at g * 14 + c
+    p.wj = 1;
+    p.wk = kDin;
+    return lat_launch<LA_GOUT, LB_NT, LE_NONE>(p, st);
+  }
+  p.A = tan + (size_t)((l - 1) & 1) * 14 * n * H;
+  return lat_launch<LA_TGATE, LB_NT, LE_NONE>(p, st);
 }
 
 }  // namespace rtn

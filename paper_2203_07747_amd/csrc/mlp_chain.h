@@ -73,13 +73,23 @@ struct LatNet {
 };
 // act: [2][n][H] ping-pong activations; sp: [L][n][H] activation derivatives;
 // g: [2][6n][H] ping-pong cotangents; y [n][6]; J [n][6][14].
+// spp (nullable): act''(a) [L][n][H]; adj (nullable): dy/dh_l [L-1][6n][H] for the
+// hidden layers below the last (dy/dh_L is W_{L+1}).
 hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const float* u, float* act, float* sp, float* y,
-                              hipStream_t st);
-hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* g, float* J, hipStream_t st);
+                              hipStream_t st, float* spp = nullptr);
+hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* g, float* J, hipStream_t st,
+                              float* adj = nullptr);
+hipError_t launch_lat_tangent(const LatNet& net, int n, int l, const float* sp, float* tan, hipStream_t st);
+// H_D [n][6][14][14] (+)= T_l^T diag(dy/dh_l (.) act''(a_l)) T_l for layer l (0-based);
+// T_0 = W_1, dy/dh_{L-1} = W_{L+1}; accumulate = 0 for the first layer visited.
+hipError_t launch_hess_accumulate(const LatNet& net, int n, int l, const float* tan, const float* adj,
+                                  const float* spp, float* Hd, int accumulate, hipStream_t st);
 
 struct QuadConst {
   float mass, Jx, Jy, Jz, arm, c_tau, g;
 };
+hipError_t launch_rk4_quadratic(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
+                                const float* JD, const float* HD, float* xn, float* A, float* B, hipStream_t st);
 hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
                                 const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st);
 

@@ -570,6 +570,71 @@ extern "C" rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, i
   return RTN_OK;
 }
 
+extern "C" rtn_status rtn_linearize_second(const rtn_model* model, int32_t prec, const rtn_quad* quad, float dt,
+                                           int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                                           const float* x, const float* u, float* x_next, float* A, float* B,
+                                           float* f_D, float* J_D, float* H_D, void* stream) {
+  if (!model) return fail(RTN_EINVAL, "model is NULL (the second-order step needs a network)");
+  if (!quad) return fail(RTN_EINVAL, "quad is NULL");
+  if (!(dt > 0.f) || !std::isfinite(dt)) return fail(RTN_EINVAL, "dt must be positive and finite");
+  if (!(quad->mass > 0.f) || !(quad->Jx > 0.f) || !(quad->Jy > 0.f) || !(quad->Jz > 0.f))
+    return fail(RTN_EINVAL, "quad mass and inertia must be positive");
+  rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
+  if (s) return s;
+  if (prec != RTN_FP32) return fail(RTN_ENOTSUP, "the second-order step is implemented in fp32 only");
+  if (n_nodes == 0) return RTN_OK;
+  if (!x || !u || !x_next || !A || !B) return fail(RTN_EINVAL, "x, u, x_next, A and B must be device pointers");
+  Model* m = const_cast<Model*>(reinterpret_cast<const Model*>(model));
+  hipStream_t st = (hipStream_t)stream;
+  QuadConst qc{quad->mass, quad->Jx, quad->Jy, quad->Jz, quad->arm, quad->c_tau, quad->g};
+  const LatNet lv = m->lat_view();
+  const int H = m->H, L = m->L;
+  const int C = n_nodes < 4096 ? n_nodes : 4096;  // nodes per chunk
+  // scratch per chunk: act [2][C][H], act' and act'' [L][C][H] each, cotangents [2][6C][H],
+  // adjoints [L-1][6C][H], tangents [2][14C][H]; outputs the caller did not ask for
+  const size_t per = (size_t)C * H;
+  const size_t nfl = per * (2 + 2 * L + 12 + 6 * (L > 1 ? L - 1 : 0) + 28) +
+                     (f_D ? 0 : (size_t)C * kDout) + (J_D ? 0 : (size_t)C * kDout * kDin) +
+                     (H_D ? 0 : (size_t)C * kDout * kDin * kDin);
+  void* dev = nullptr;
+  hipError_t e = hipMallocAsync(&dev, nfl * 4, st);
+  if (e != hipSuccess) return fail(RTN_ENOMEM, "hipMallocAsync(%zu bytes): %s", nfl * 4, hipGetErrorString(e));
+  float* act = static_cast<float*>(dev);
+  float* sp = act + 2 * per;
+  float* spp = sp + (size_t)L * per;
+  float* g = spp + (size_t)L * per;
+  float* adj = g + 12 * per;
+  float* tan = adj + 6 * per * (L > 1 ? L - 1 : 0);
+  float* extra = tan + 28 * per;
+  float* yw = f_D ? nullptr : extra;
+  extra += f_D ? 0 : (size_t)C * kDout;
+  float* Jw = J_D ? nullptr : extra;
+  extra += J_D ? 0 : (size_t)C * kDout * kDin;
+  float* Hw = H_D ? nullptr : extra;
+  for (int c0 = 0; c0 < n_nodes && e == hipSuccess; c0 += C) {
+    const int nc = n_nodes - c0 < C ? n_nodes - c0 : C;
+    const float* xc = x + (size_t)c0 * kNx;
+    const float* uc = u + (size_t)c0 * kNu;
+    float* y = f_D ? f_D + (size_t)c0 * kDout : yw;
+    float* J = J_D ? J_D + (size_t)c0 * kDout * kDin : Jw;
+    float* Hd = H_D ? H_D + (size_t)c0 * kDout * kDin * kDin : Hw;
+    ProfScope ps("linearize_second", st);
+    if ((e = launch_lat_forward(lv, nc, xc, uc, act, sp, y, st, spp)) != hipSuccess) break;
+    if ((e = launch_lat_reverse(lv, nc, sp, g, J, st, L > 1 ? adj : nullptr)) != hipSuccess) break;
+    for (int l = 0; l < L && e == hipSuccess; ++l) {
+      if (l >= 1 && (e = launch_lat_tangent(lv, nc, l, sp, tan, st)) != hipSuccess) break;
+      e = launch_hess_accumulate(lv, nc, l, tan, adj, spp, Hd, l > 0, st);
+    }
+    if (e != hipSuccess) break;
+    e = launch_rk4_quadratic(nc, qc, dt, xc, uc, y, J, Hd, x_next + (size_t)c0 * kNx, A + (size_t)c0 * kNx * kNx,
+                             B + (size_t)c0 * kNx * kNu, st);
+  }
+  hipError_t e2 = hipFreeAsync(dev, st);
+  if (e != hipSuccess) return hip_fail(e, "rtn_linearize_second");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return RTN_OK;
+}
+
 extern "C" rtn_status rtn_riccati_box(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes, const float* A,
                                       const float* B, const double* c, const double* Q_host, const double* R_host,
                                       const double* QN_host, const double* q, const double* r, const double* qN,

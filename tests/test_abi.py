@@ -113,6 +113,17 @@ def test_riccati_validation(lib):
                            z, z, None, None) == RTN_EINVAL
 
 
+def test_linearize_second_validation(lib):
+    q = Quad(QUAD.mass, QUAD.Jx, QUAD.Jy, QUAD.Jz, QUAD.arm, QUAD.c_tau, QUAD.g)
+    z = ctypes.c_void_p(16)
+    f = lambda model, prec, n: lib.rtn_linearize_second(model, prec, ctypes.byref(q), ctypes.c_float(0.05), 1, None,
+                                                        n, z, z, z, z, z, None, None, None, None)
+    assert f(None, 0, 4) == RTN_EINVAL                      # model required
+    assert f(z, 1, 4) == RTN_ENOTSUP                        # fp32 only
+    assert lib.rtn_linearize_second(z, 0, None, ctypes.c_float(0.05), 1, None, 4, z, z, z, z, z, None, None, None,
+                                    None) == RTN_EINVAL     # quad
+
+
 def test_riccati_box_validation(lib):
     Q = np.eye(13); R = 0.1 * np.eye(4)
     qp = Q.ctypes.data_as(ctypes.c_void_p); rp = R.ctypes.data_as(ctypes.c_void_p)

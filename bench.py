@@ -209,6 +209,18 @@ def extras(torch, rtn, lin_out, off, stream):
                                  "tile_choice": tile_choice(rtn, "fp32", cfg.width, cfg.n_hidden, x.shape[0]),
                                  "kernel_us_unbatched": {k: v["avg_ms"] * 1e3 for k, v in kern.items()}}
         m.close()
+    # second-order local approximation (fp32): one instance (c2) and a 4096-node batch of the c2 network
+    cfg, o, x, u, Ws, bs = config_workload("c2")
+    m = rtn.Model(Ws, bs)
+    for label, reps in (("c2", 1), ("c2_x205", 205)):
+        xt = torch.from_numpy(np.tile(x, (reps, 1))).cuda()
+        ut = torch.from_numpy(np.tile(u, (reps, 1))).cuda()
+        sout = {}
+        f = lambda: rtn.linearize_second(xt, ut, m, cfg.dt, out=sout, stream=stream)
+        ms, _ = time_steps(torch, f, 20, 3, stream)
+        res[f"second_order_{label}"] = {"nodes": int(xt.shape[0]), "ms_per_call": ms,
+                                        "nodes_per_s": xt.shape[0] / (ms * 1e-3)}
+    m.close()
     Q = np.eye(13); R = 0.1 * np.eye(4)
     rout = {}
     f = lambda: rtn.riccati(lin_out["A"], lin_out["B"], Q, R, Q, offsets=off, out=rout, stream=stream)

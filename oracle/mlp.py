@@ -30,6 +30,46 @@ Z_U = slice(10, 14)  # u
 Z_TO_X = np.array([7, 8, 9, 10, 11, 12, 3, 4, 5, 6])
 
 
+# residual input variants (Sec. VI, simplified residual models): the full model
+# [v, w, q, u] -> 6 outputs, and the linear-acceleration models f_Da(v_B) and
+# f_Da,u(v_B, u) -> 3 outputs, v_B = conj(q) (.) v the body-frame velocity
+INPUT_FULL, INPUT_VB, INPUT_VB_U = 0, 1, 2
+D_IN = {INPUT_FULL: 14, INPUT_VB: 3, INPUT_VB_U: 7}
+D_OUT = {INPUT_FULL: 6, INPUT_VB: 3, INPUT_VB_U: 3}
+
+
+def body_velocity(x: np.ndarray) -> np.ndarray:
+    """v_B = conj(q) (.) v (the homogeneous form, like every q (.) v here)."""
+    from .quadrotor import quat_conj, quat_rotate
+    return quat_rotate(quat_conj(x[:, 3:7]), x[:, 7:10])
+
+
+def pack_input_mode(x: np.ndarray, u: np.ndarray, mode: int) -> np.ndarray:
+    if mode == INPUT_FULL:
+        return pack_input(x, u)
+    vb = body_velocity(np.asarray(x))
+    return vb if mode == INPUT_VB else np.concatenate([vb, np.asarray(u, dtype=vb.dtype)], axis=1)
+
+
+def input_jacobian(x: np.ndarray, u: np.ndarray, mode: int):
+    """(dz/dx (n, d_in, 13), dz/du (n, d_in, 4)) of the network input at (x, u), by
+    complex-step differentiation of pack_input_mode (exact to rounding)."""
+    x = np.asarray(x, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    n, h = x.shape[0], 1e-30
+    dzx = np.zeros((n, D_IN[mode], 13))
+    dzu = np.zeros((n, D_IN[mode], 4))
+    for i in range(13):
+        xc = x.astype(complex)
+        xc[:, i] += 1j * h
+        dzx[:, :, i] = pack_input_mode(xc, u.astype(complex), mode).imag / h
+    for i in range(4):
+        uc = u.astype(complex)
+        uc[:, i] += 1j * h
+        dzu[:, :, i] = pack_input_mode(x.astype(complex), uc, mode).imag / h
+    return dzx, dzu
+
+
 def pack_input(x: np.ndarray, u: np.ndarray) -> np.ndarray:
     x = np.asarray(x, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
@@ -135,6 +175,22 @@ def residual_in_state(y: np.ndarray, J: np.ndarray):
     J_x[:, 7:13, Z_TO_X] = J[:, :, 0:10]
     J_u = np.zeros((n, 13, 4))
     J_u[:, 7:13, :] = J[:, :, 10:14]
+    return f_bar, J_x, J_u
+
+
+def residual_in_state_mode(y: np.ndarray, J: np.ndarray, x: np.ndarray, u: np.ndarray, mode: int):
+    """As residual_in_state for any input variant: the outputs fill v-dot (and w-dot for
+    the full model); the state/input Jacobians are J dz/dx and J dz/du at the node."""
+    if mode == INPUT_FULL:
+        return residual_in_state(y, J)
+    n, d = y.shape
+    dzx, dzu = input_jacobian(x, u, mode)
+    f_bar = np.zeros((n, 13))
+    f_bar[:, 7:7 + d] = y
+    J_x = np.zeros((n, 13, 13))
+    J_x[:, 7:7 + d, :] = J @ dzx
+    J_u = np.zeros((n, 13, 4))
+    J_u[:, 7:7 + d, :] = J @ dzu
     return f_bar, J_x, J_u
 
 

@@ -28,7 +28,7 @@ import numpy as np
 
 from workload import QUAD, QuadParams
 from .quadrotor import nominal_f, nominal_jac
-from .mlp import MLP, pack_input, residual_in_state
+from .mlp import MLP, pack_input, residual_in_state, pack_input_mode, residual_in_state_mode, INPUT_FULL
 
 RK4_C = (0.0, 0.5, 0.5, 1.0)
 RK4_W = (1.0, 2.0, 2.0, 1.0)
@@ -43,17 +43,18 @@ def rk4_step(f, x: np.ndarray, u: np.ndarray, dt: float) -> np.ndarray:
     return x + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
-def node_parameters(model: Optional[MLP], x: np.ndarray, u: np.ndarray):
-    """f_D-bar (n,6), J_D (n,6,14) at the nodes (zeros without a network)."""
+def node_parameters(model: Optional[MLP], x: np.ndarray, u: np.ndarray, mode: int = INPUT_FULL):
+    """f_D-bar (n,d_out), J_D (n,d_out,d_in) at the nodes (zeros without a network)."""
     n = x.shape[0]
     if model is None:
         return np.zeros((n, 6)), np.zeros((n, 6, 14))
-    return model.jacobian(pack_input(x, u))
+    return model.jacobian(pack_input_mode(x, u, mode))
 
 
-def affine_field(x_k, u_k, y_bar, J, quad: QuadParams = QUAD):
+def affine_field(x_k, u_k, y_bar, J, quad: QuadParams = QUAD, mode: int = INPUT_FULL):
     """The frozen-parameter vector field F(x, u) = f_F(x, u) + f_D*(x, u)."""
-    f_bar, J_x, J_u = residual_in_state(y_bar, J)
+    f_bar, J_x, J_u = residual_in_state_mode(np.asarray(y_bar, np.float64), np.asarray(J, np.float64),
+                                             np.asarray(x_k, np.float64), np.asarray(u_k, np.float64), mode)
     x_k = np.asarray(x_k, dtype=np.float64)
     u_k = np.asarray(u_k, dtype=np.float64)
 
@@ -66,19 +67,22 @@ def affine_field(x_k, u_k, y_bar, J, quad: QuadParams = QUAD):
 
 
 def linearize_affine(x: np.ndarray, u: np.ndarray, model: Optional[MLP], dt: float,
-                     quad: QuadParams = QUAD, params=None):
-    """(x_next (n,13), A (n,13,13), B (n,13,4), f_D-bar (n,6), J_D (n,6,14)).
+                     quad: QuadParams = QUAD, params=None, mode: int = INPUT_FULL):
+    """(x_next (n,13), A (n,13,13), B (n,13,4), f_D-bar (n,d_out), J_D (n,d_out,d_in)).
 
     ``params`` = (f_D-bar, J_D) supplies the local approximation's parameters
-    directly (e.g. from a reduced-precision evaluation of the network)."""
+    directly (e.g. from a reduced-precision evaluation of the network); ``mode``
+    selects the residual's input variant (the Jacobian w.r.t. the state then goes
+    through v_B = conj(q) (.) v at the node)."""
     x = np.asarray(x, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
     n = x.shape[0]
     if params is None:
-        y_bar, J = node_parameters(model, x, u)
+        y_bar, J = node_parameters(model, x, u, mode)
     else:
         y_bar, J = (np.asarray(a, dtype=np.float64) for a in params)
-    f_bar, J_x, J_u = residual_in_state(y_bar, J)
+    f_bar, J_x, J_u = residual_in_state_mode(y_bar, J, x, u, mode) if model is not None or params is not None \
+        else residual_in_state(y_bar, J)
 
     # S = d x_s / d [x_k, u_k] (n, 13, 17); stage derivative K_s and dK_s.
     S0 = np.zeros((n, 13, 17))
@@ -106,9 +110,9 @@ def linearize_affine(x: np.ndarray, u: np.ndarray, model: Optional[MLP], dt: flo
 
 
 def affine_phi(x0: np.ndarray, u0: np.ndarray, x_k, u_k, y_bar, J, dt: float,
-               quad: QuadParams = QUAD) -> np.ndarray:
+               quad: QuadParams = QUAD, mode: int = INPUT_FULL) -> np.ndarray:
     """phi(x0, u0) with the local approximation frozen at (x_k, u_k, y_bar, J)."""
-    return rk4_step(affine_field(x_k, u_k, y_bar, J, quad), np.asarray(x0, np.float64),
+    return rk4_step(affine_field(x_k, u_k, y_bar, J, quad, mode), np.asarray(x0, np.float64),
                     np.asarray(u0, np.float64), dt)
 
 

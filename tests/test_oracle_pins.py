@@ -537,3 +537,92 @@ def test_second_order_approximation_error_is_third_order():
     sA = np.polyfit(np.log(dts), np.log(eA), 1)[0]
     assert abs(sx - 4) < 0.35, sx
     assert abs(sA - 3) < 0.5, sA
+
+
+# ---------------------------------------------------------------- residual input variants (f_Da, f_Da,u)
+
+def _variant_net(din, seed=0):
+    rng = np.random.default_rng(seed)
+    Ws = [rng.normal(size=(32, din)) * 0.3, rng.normal(size=(32, 32)) * 0.2, rng.normal(size=(3, 32)) * 0.3]
+    bs = [rng.normal(size=32) * 0.1, rng.normal(size=32) * 0.1, rng.normal(size=3) * 0.1]
+    return Ws, bs
+
+
+def test_body_velocity_identity_and_norm():
+    from oracle.mlp import body_velocity
+    x, _ = sample_nodes(50, seed=11)
+    x = x.astype(np.float64)
+    vb = body_velocity(x)
+    qn2 = np.sum(x[:, 3:7] ** 2, axis=1)
+    np.testing.assert_allclose(np.linalg.norm(vb, axis=1), qn2 * np.linalg.norm(x[:, 7:10], axis=1), rtol=1e-12)
+    xi = x.copy()
+    xi[:, 3:7] = [1, 0, 0, 0]
+    np.testing.assert_allclose(body_velocity(xi), xi[:, 7:10], atol=1e-15)
+    # a yaw of +90 degrees maps world x to body -y
+    xq = x[:1].copy()
+    xq[0, 3:7] = [np.cos(np.pi / 4), 0, 0, np.sin(np.pi / 4)]
+    xq[0, 7:10] = [1, 0, 0]
+    np.testing.assert_allclose(body_velocity(xq)[0], [0, -1, 0], atol=1e-15)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_input_jacobian_matches_finite_differences(mode):
+    from oracle.mlp import input_jacobian, pack_input_mode
+    x, u = sample_nodes(6, seed=12)
+    x, u = x.astype(np.float64), u.astype(np.float64)
+    dzx, dzu = input_jacobian(x, u, mode)
+    eps = 1e-6
+    for i in range(13):
+        xp, xm = x.copy(), x.copy()
+        xp[:, i] += eps
+        xm[:, i] -= eps
+        np.testing.assert_allclose(dzx[:, :, i], (pack_input_mode(xp, u, mode) - pack_input_mode(xm, u, mode)) / (2 * eps),
+                                   atol=1e-8)
+    for i in range(4):
+        up, um = u.copy(), u.copy()
+        up[:, i] += eps
+        um[:, i] -= eps
+        np.testing.assert_allclose(dzu[:, :, i], (pack_input_mode(x, up, mode) - pack_input_mode(x, um, mode)) / (2 * eps),
+                                   atol=1e-8)
+
+
+@pytest.mark.parametrize("mode,din", [(1, 3), (2, 7)])
+def test_variant_linearisation_matches_finite_differences(mode, din):
+    Ws, bs = _variant_net(din)
+    net = MLP(Ws, bs)
+    x, u = sample_nodes(5, seed=13)
+    xn, A, B, yb, J = linearize_affine(x, u, net, 0.05, mode=mode)
+    assert yb.shape == (5, 3) and J.shape == (5, 3, din)
+    eps = 1e-6
+    for j in range(13):
+        xp, xm = x.astype(float).copy(), x.astype(float).copy()
+        xp[:, j] += eps
+        xm[:, j] -= eps
+        fd = (affine_phi(xp, u, x, u, yb, J, 0.05, mode=mode) - affine_phi(xm, u, x, u, yb, J, 0.05, mode=mode)) / (2 * eps)
+        np.testing.assert_allclose(A[:, :, j], fd, atol=1e-7)
+    for j in range(4):
+        up, um = u.astype(float).copy(), u.astype(float).copy()
+        up[:, j] += eps
+        um[:, j] -= eps
+        fd = (affine_phi(x, up, x, u, yb, J, 0.05, mode=mode) - affine_phi(x, um, x, u, yb, J, 0.05, mode=mode)) / (2 * eps)
+        np.testing.assert_allclose(B[:, :, j], fd, atol=1e-7)
+
+
+def test_variant_at_level_attitude_equals_full_model_embedding():
+    """With q = identity, v_B = v: a v_B network gives the same step as the full-input
+    network whose first layer reads v (other inputs weighted 0) and whose angular outputs
+    are 0 -- as long as the attitude stays put during the step (zero body rates and equal
+    thrusts, so no torque), since the v_B model also depends on q."""
+    Ws, bs = _variant_net(3, seed=4)
+    x, u = sample_nodes(8, seed=14)
+    x = x.astype(np.float64)
+    x[:, 3:7] = [1, 0, 0, 0]
+    x[:, 10:13] = 0.0
+    u = np.repeat(u[:, :1], 4, axis=1)
+    W1 = np.zeros((32, 14)); W1[:, 0:3] = Ws[0]
+    Wo = np.zeros((6, 32)); Wo[0:3] = Ws[2]
+    bo = np.zeros(6); bo[0:3] = bs[2]
+    full = MLP([W1, Ws[1], Wo], [bs[0], bs[1], bo])
+    xv = linearize_affine(x, u, MLP(Ws, bs), 0.05, mode=1)[0]
+    xf = linearize_affine(x, u, full, 0.05)[0]
+    np.testing.assert_allclose(xv, xf, atol=1e-13)

@@ -64,16 +64,26 @@ typedef enum { RTN_FP32 = 0, RTN_BF16 = 1, RTN_FP8 = 2 } rtn_precision;
 /* Hidden-layer activation: SiLU a*logistic(a), or identity (linear network). */
 typedef enum { RTN_ACT_SILU = 0, RTN_ACT_IDENTITY = 1 } rtn_activation;
 
+/* Residual model variants (Sec. VI): the full residual of eq. (7) with input
+ * [v, omega, q, u] and outputs [v-dot (world), omega-dot (body)], or the
+ * simplified linear-acceleration residuals f_Da(v_B) and f_Da,u(v_B, u) whose
+ * input is the body-frame velocity v_B = conj(q) (.) v (and u) and whose three
+ * outputs add to v-dot; omega-dot gets no residual. */
+typedef enum { RTN_INPUT_FULL = 0, RTN_INPUT_VB = 1, RTN_INPUT_VB_U = 2 } rtn_input;
+
 /* Residual network descriptor (naming N-L-W of Sec. VII: L hidden layers of
- * width W).  d_in must be 14 (input [v, omega, q, u]) and d_out 6 (linear and
- * angular acceleration residuals, eq. (7)).  width must be one of 64, 128, 256,
- * 512, 1024; 1 <= n_hidden <= 16. */
+ * width W).  (input, d_in, d_out) must be (RTN_INPUT_FULL, 14, 6),
+ * (RTN_INPUT_VB, 3, 3) or (RTN_INPUT_VB_U, 7, 3); width one of 64, 128, 256,
+ * 512, 1024; 1 <= n_hidden <= 16.  The variants support rtn_linearize and
+ * calibration; training, rtn_linearize_exact and rtn_linearize_second return
+ * RTN_ENOTSUP for them. */
 typedef struct {
     int32_t d_in;
     int32_t d_out;
     int32_t n_hidden;
     int32_t width;
     int32_t activation; /* rtn_activation */
+    int32_t input;      /* rtn_input */
 } rtn_mlp_desc;
 
 /* Quadrotor constants of eq. (6): mass [kg], diagonal inertia [kg m^2], arm =
@@ -145,6 +155,11 @@ rtn_status rtn_model_get_scales(const rtn_model* model, float* scales_host, int3
  *   B          [n][13][4]   B[k][i][j] = d x_{k+1,i} / d u_{k,j}
  *   f_D        nullable [n][6]      network output at the node (f_D-bar)
  *   J_D        nullable [n][6][14]  its Jacobian w.r.t. [v, omega, q, u]
+ *              For the variants (RTN_INPUT_VB, RTN_INPUT_VB_U) both hold the
+ *              network in the same embedded layout: outputs 0..2 are the
+ *              v-dot residual and 3..5 zero; J_D columns 0..2 are d/d v_B,
+ *              10..13 d/du (VB_U only), the rest zero.  The state Jacobian
+ *              J_D dv_B/dx (through q and v) is formed inside the step.
  *   status     nullable uint8 [n]: 0 ok; bit0 non-finite network output or
  *              Jacobian; bit1 non-finite x_next, A or B.
  * The linearisation point (x_k, u_k, f_D-bar, J_D) is held fixed inside the RK4

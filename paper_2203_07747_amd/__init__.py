@@ -13,7 +13,7 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import PREC, ACT, MlpDesc, Quad, check, load
+from ._lib import PREC, ACT, INPUT, MlpDesc, Quad, check, load
 
 __all__ = ["Model", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
@@ -103,10 +103,14 @@ def quad_struct(q) -> Quad:
 class Model:
     """A residual network owned by the library (fp32 master weights on the GPU)."""
 
-    def __init__(self, Ws: Sequence[np.ndarray], bs: Sequence[np.ndarray], activation: str = "silu"):
+    def __init__(self, Ws: Sequence[np.ndarray], bs: Sequence[np.ndarray], activation: str = "silu",
+                 input: str = "full"):
+        """input: "full" ([v, omega, q, u] -> 6 outputs), "vb" (v_B -> 3) or "vb_u"
+        ([v_B, u] -> 3), the residual variants of Sec. VI."""
         L = len(Ws) - 1
         width = Ws[0].shape[0]
-        self.desc = MlpDesc(Ws[0].shape[1], Ws[-1].shape[0], L, width, ACT[activation])
+        self.input = input
+        self.desc = MlpDesc(Ws[0].shape[1], Ws[-1].shape[0], L, width, ACT[activation], INPUT[input])
         self.n_hidden, self.width = L, width
         flat = self._flatten(Ws, bs)
         n = ctypes.c_int64()

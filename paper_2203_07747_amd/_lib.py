@@ -15,12 +15,13 @@ P = ctypes.POINTER
 
 RTN_OK, RTN_EINVAL, RTN_ENOMEM, RTN_EHIP, RTN_ENOTSUP = 0, -1, -2, -3, -4
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+INPUT = {"full": 0, "vb": 1, "vb_u": 2}
 ACT = {"silu": 0, "identity": 1}
 
 
 class MlpDesc(ctypes.Structure):
     _fields_ = [("d_in", c_int32), ("d_out", c_int32), ("n_hidden", c_int32), ("width", c_int32),
-                ("activation", c_int32)]
+                ("activation", c_int32), ("input", c_int32)]
 
 
 class Quad(ctypes.Structure):

@@ -382,7 +382,7 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
   const float* dq = net.wscale;  // fp8 only
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int row0 = blk * R;
-    // z_0 = [v, omega, q, u] into operand slots of K1 features
+    // z_0 (the network input features) into operand slots of K1 features
     for (int it = tid; it < C::RT * C::KS_1 * kWave; it += NW * kWave) {
       const int l = it % kWave, s = (it / kWave) % C::KS_1, rt = it / (kWave * C::KS_1);
       const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
@@ -391,12 +391,8 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
       for (int j = 0; j < C::E; ++j) {
         const int k = slot_feature(s * C::E + j, gg);
         float z = 0.f;
-        if (row < n && k < kDin) {
-          if (zin) z = zin[(size_t)row * kDin + k];
-          else if (k < 6) z = x[(size_t)row * kNx + 7 + k];          // v, omega
-          else if (k < 10) z = x[(size_t)row * kNx + 3 + (k - 6)];   // q
-          else z = u[(size_t)row * kNu + (k - 10)];                  // u
-        }
+        if (row < n && k < kDin)
+          z = zin ? zin[(size_t)row * kDin + k] : net_feature(x + (size_t)row * kNx, u + (size_t)row * kNu, k, net.input);
         v[j] = z;
       }
       if (amax) {  // calibration only: max |z_0| (padding slots hold zeros)

@@ -39,6 +39,28 @@ __host__ __device__ inline int slot_feature(int q, int g) {
   return 32 * (q >> 4) + ((q & 15) >> 2) * 8 + g * 4 + (q & 3);
 }
 
+// Network input feature k (0..13) of one node, xr = x row (13), ur = u row (4).
+// input 0: z = [v, omega, q, u].  Inputs 1 and 2 are the simplified residual
+// models of Sec. VI, fed the body-frame velocity v_B = conj(q) (.) v = R(q)^T v
+// (homogeneous in q, like every q (.) v product of eq. (6)) in slots 0..2 and,
+// for input 2, u in slots 10..13; every other slot is zero.
+__device__ inline float net_feature(const float* __restrict__ xr, const float* __restrict__ ur, int k, int input) {
+  if (input == 0) {
+    if (k < 6) return xr[7 + k];
+    if (k < 10) return xr[3 + (k - 6)];
+    return ur[k - 10];
+  }
+  if (k < 3) {
+    const float w = xr[3], a = xr[4], b = xr[5], c = xr[6];
+    const float v0 = xr[7], v1 = xr[8], v2 = xr[9];
+    if (k == 0) return (w * w + a * a - b * b - c * c) * v0 + 2.f * (a * b + w * c) * v1 + 2.f * (a * c - w * b) * v2;
+    if (k == 1) return 2.f * (a * b - w * c) * v0 + (w * w - a * a + b * b - c * c) * v1 + 2.f * (b * c + w * a) * v2;
+    return 2.f * (a * c + w * b) * v0 + 2.f * (b * c - w * a) * v1 + (w * w - a * a - b * b + c * c) * v2;
+  }
+  if (input == 2 && k >= 10) return ur[k - 10];
+  return 0.f;
+}
+
 // Inverse for one 32-feature tile: position of feature k in "stash order"
 // (tile, group, register), used for per-feature side arrays (the activation
 // derivative stash) that are read by the same lane mapping.

@@ -46,17 +46,14 @@ struct LatArgs {
   float* dout;                 // LE_SILU: act'(a) [M][N]; LE_GATE (nullable): the ungated value [M][N]
   float* ddout;                // LE_SILU (nullable): act''(a) [M][N]
   int act;                     // LE_SILU: 0 SiLU, 1 identity
+  int input;                   // LA_Z0: network input variant (net_feature)
 };
 
 constexpr int kLatWaves = 16;
 
 __device__ inline float lat_a(const LatArgs& p, int akind, int r, int k) {
   if (r >= p.M || k >= p.K) return 0.f;
-  if (akind == LA_Z0) {
-    if (k < 6) return p.x[(size_t)r * kNx + 7 + k];       // v, omega
-    if (k < 10) return p.x[(size_t)r * kNx + 3 + (k - 6)]; // q
-    return p.u[(size_t)r * kNu + (k - 10)];                 // u
-  }
+  if (akind == LA_Z0) return net_feature(p.x + (size_t)r * kNx, p.u + (size_t)r * kNu, k, p.input);
   if (akind == LA_ACT) return p.A[(size_t)r * p.K + k];
   const int node = r / p.rpn, j = r - p.rpn * node;
   const float g = p.gate_a[(size_t)node * p.K + k];
@@ -157,6 +154,7 @@ hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const fl
     p.dout = sp + (size_t)l * n * H;
     p.ddout = spp ? spp + (size_t)l * n * H : nullptr;
     p.act = net.act;
+    p.input = net.input;
     e = l == 0 ? lat_launch<LA_Z0, LB_NT, LE_SILU>(p, st) : lat_launch<LA_ACT, LB_NT, LE_SILU>(p, st);
     if (e != hipSuccess) return e;
   }

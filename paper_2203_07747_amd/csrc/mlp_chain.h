@@ -12,8 +12,9 @@ namespace rtn {
 // 0-based: fw[i] packs W_{i+1} (M = fan_out, K = fan_in), rw[i] packs W_{i+1}^T
 // (M = fan_in, K = fan_out) for the hidden layers i < L.
 struct NetView {
-  int L;    // hidden layers
-  int act;  // 0 SiLU, 1 identity
+  int L;      // hidden layers
+  int act;    // 0 SiLU, 1 identity
+  int input;  // network input: 0 [v, w, q, u]; 1 v_B; 2 [v_B, u] (v_B in slots 0..2, u in 10..13)
   const void* fw[17];
   const void* rw[16];
   const float* bias[17];
@@ -67,7 +68,7 @@ hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st)
 // Small-batch per-layer path (layer_lat.hip), fp32 master weights: W[l] is
 // W_{l+1} row-major [fan_out][fan_in], W[L] the output layer.
 struct LatNet {
-  int L, H, act;
+  int L, H, act, input;
   const float* W[17];
   const float* b[17];
 };
@@ -90,8 +91,10 @@ struct QuadConst {
 };
 hipError_t launch_rk4_quadratic(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
                                 const float* JD, const float* HD, float* xn, float* A, float* B, hipStream_t st);
+// input: network input variant of JD's columns (0 full; 1, 2 body velocity)
 hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
-                                const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st);
+                                const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st,
+                                int input = 0);
 
 hipError_t launch_rk4_exact_stage(int n, int stage, const QuadConst& q, float dt, const float* x, const float* u,
                                   const float* fD, const float* JD, float* xs, float* kp, float* kacc, float* dkp,

@@ -12,7 +12,9 @@
 namespace rtn {
 
 struct Model {
-  rtn_mlp_desc desc{};
+  rtn_mlp_desc desc{};       // internal layout: d_in 14, d_out 6
+  rtn_mlp_desc user_desc{};  // as created (the variants have 3 or 7 inputs, 3 outputs)
+  int input = RTN_INPUT_FULL;
   int L = 0, H = 0;
   int64_t n_params = 0;
   int64_t w_off[kMaxHidden + 1] = {}, b_off[kMaxHidden + 1] = {};
@@ -72,6 +74,9 @@ struct Model {
   rtn_status ensure_packed(int prec, hipStream_t st);
   rtn_status ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st);
   NetView view(int prec) const;
+  int in_col(int c) const;
+  std::vector<float> expand(const float* user) const;         // user parameter layout -> internal
+  void contract(const float* internal, float* user) const;    // internal -> user layout
   LatNet lat_view() const;
   rtn_status ensure_lat_workspace(int64_t n, hipStream_t st);
   rtn_status ensure_train_workspace(int64_t batch, hipStream_t st);

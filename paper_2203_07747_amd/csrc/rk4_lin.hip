@@ -25,6 +25,37 @@ constexpr int kNodesPerBlock = 16;
 constexpr int kNodeStride = 108;  // x 13 | u 4 | y 6 | J 84 | pad 1
 
 
+// Network Jacobian J (w.r.t. the input slots) -> the residual's state Jacobian
+// in the slot layout of the full input [v, omega, q, u], at the node x_k, for the
+// body-velocity inputs: slots 0..2 hold v_B = R(q)^T v, so the v columns become
+// J dv_B/dv = J R^T, the q columns J dv_B/dq (homogeneous in q), omega's are
+// zero; the u slots are unchanged.  One row of six floats per call.
+__device__ inline void vb_row_to_state(const float* xk, float* Jr) {
+  const float w = xk[3], a = xk[4], b = xk[5], c = xk[6];
+  const float v0 = xk[7], v1 = xk[8], v2 = xk[9];
+  const float j0 = Jr[0], j1 = Jr[1], j2 = Jr[2];
+  // R(q) (rows) of the homogeneous rotation q (.) p (.) conj(q)
+  const float R00 = w * w + a * a - b * b - c * c, R01 = 2.f * (a * b - w * c), R02 = 2.f * (a * c + w * b);
+  const float R10 = 2.f * (a * b + w * c), R11 = w * w - a * a + b * b - c * c, R12 = 2.f * (b * c - w * a);
+  const float R20 = 2.f * (a * c - w * b), R21 = 2.f * (b * c + w * a), R22 = w * w - a * a - b * b + c * c;
+  // d v_B / d v_i = column i of R^T = row i of R
+  Jr[0] = j0 * R00 + j1 * R01 + j2 * R02;
+  Jr[1] = j0 * R10 + j1 * R11 + j2 * R12;
+  Jr[2] = j0 * R20 + j1 * R21 + j2 * R22;
+  Jr[3] = Jr[4] = Jr[5] = 0.f;
+  // d v_B / d (w, a, b, c): derivative of sum_i R_ic(q) v_i
+  const float d0w = 2.f * (w * v0 + c * v1 - b * v2), d0a = 2.f * (a * v0 + b * v1 + c * v2);
+  const float d0b = 2.f * (-b * v0 + a * v1 - w * v2), d0c = 2.f * (-c * v0 + w * v1 + a * v2);
+  const float d1w = 2.f * (-c * v0 + w * v1 + a * v2), d1a = 2.f * (b * v0 - a * v1 + w * v2);
+  const float d1b = 2.f * (a * v0 + b * v1 + c * v2), d1c = 2.f * (-w * v0 - c * v1 + b * v2);
+  const float d2w = 2.f * (b * v0 - a * v1 + w * v2), d2a = 2.f * (c * v0 - w * v1 - a * v2);
+  const float d2b = 2.f * (w * v0 + c * v1 - b * v2), d2c = 2.f * (a * v0 + b * v1 + c * v2);
+  Jr[6] = j0 * d0w + j1 * d1w + j2 * d2w;
+  Jr[7] = j0 * d0a + j1 * d1a + j2 * d2a;
+  Jr[8] = j0 * d0b + j1 * d1b + j2 * d2b;
+  Jr[9] = j0 * d0c + j1 * d1c + j2 * d2c;
+}
+
 // J_x d restricted to rows 7..12 (network inputs are v, omega, q).
 __device__ inline void residual_tangent(const float* J, const float* d, float* out6) {
 #pragma unroll
@@ -42,7 +73,7 @@ __device__ inline void residual_tangent(const float* J, const float* d, float* o
 __global__ void __launch_bounds__(256)
 rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, const float* __restrict__ u,
                      const float* __restrict__ fD, const float* __restrict__ JD, float* __restrict__ xn,
-                     float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status) {
+                     float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status, int input) {
   __shared__ float sm[kNodesPerBlock * kNodeStride];
   __shared__ int flags[kNodesPerBlock];
   const int tid = threadIdx.x;
@@ -58,6 +89,13 @@ rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, 
     sm[(i / (kDout * kDin)) * kNodeStride + 23 + (i % (kDout * kDin))] = JD ? JD[(size_t)node0 * kDout * kDin + i] : 0.f;
   if (tid < kNodesPerBlock) flags[tid] = 0;
   __syncthreads();
+  if (input != 0 && JD) {  // uniform over the block
+    if (tid < nn * kDout) {
+      float* sn = sm + (tid / kDout) * kNodeStride;
+      vb_row_to_state(sn, sn + 23 + (tid % kDout) * kDin);
+    }
+    __syncthreads();
+  }
 
   const int ln = tid >> 4, c = tid & 15;
   const bool active = ln < nn;
@@ -174,10 +212,11 @@ rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, 
 }
 
 hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
-                                const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st) {
+                                const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st,
+                                int input) {
   if (n <= 0) return hipSuccess;
   const int blocks = (n + kNodesPerBlock - 1) / kNodesPerBlock;
-  rk4_linearize_kernel<<<blocks, 256, 0, st>>>(n, q, dt, x, u, fD, JD, xn, A, B, status);
+  rk4_linearize_kernel<<<blocks, 256, 0, st>>>(n, q, dt, x, u, fD, JD, xn, A, B, status, input);
   return hipGetLastError();
 }
 

@@ -53,14 +53,25 @@ static bool width_supported(int w) { return w == 64 || w == 128 || w == 256 || w
 
 static rtn_status check_desc(const rtn_mlp_desc* d) {
   if (!d) return fail(RTN_EINVAL, "desc is NULL");
-  if (d->d_in != kDin) return fail(RTN_EINVAL, "d_in must be 14 (got %d)", d->d_in);
-  if (d->d_out != kDout) return fail(RTN_EINVAL, "d_out must be 6 (got %d)", d->d_out);
+  if (d->input < RTN_INPUT_FULL || d->input > RTN_INPUT_VB_U) return fail(RTN_EINVAL, "unknown input variant %d", d->input);
+  const int din = d->input == RTN_INPUT_FULL ? kDin : (d->input == RTN_INPUT_VB ? 3 : 7);
+  const int dout = d->input == RTN_INPUT_FULL ? kDout : 3;
+  if (d->d_in != din) return fail(RTN_EINVAL, "d_in must be %d for this input variant (got %d)", din, d->d_in);
+  if (d->d_out != dout) return fail(RTN_EINVAL, "d_out must be %d for this input variant (got %d)", dout, d->d_out);
   if (d->n_hidden < 1 || d->n_hidden > kMaxHidden)
     return fail(RTN_EINVAL, "n_hidden must be in [1, 16] (got %d)", d->n_hidden);
   if (d->activation != RTN_ACT_SILU && d->activation != RTN_ACT_IDENTITY)
     return fail(RTN_EINVAL, "unknown activation %d", d->activation);
   if (d->width <= 0) return fail(RTN_EINVAL, "width must be positive (got %d)", d->width);
   if (!width_supported(d->width)) return fail(RTN_ENOTSUP, "width %d not supported (64, 128, 256, 512, 1024)", d->width);
+  return RTN_OK;
+}
+
+// Training and the exact / second-order linearisations work on the full
+// residual network only.
+static rtn_status full_only(const Model* m, const char* what) {
+  if (m->input != RTN_INPUT_FULL)
+    return fail(RTN_ENOTSUP, "%s is implemented for the full residual network (input RTN_INPUT_FULL) only", what);
   return RTN_OK;
 }
 
@@ -104,12 +115,52 @@ void rtn::Model::release(void* p) {
   (void)hipFree(p);
 }
 
+// Internal column of user first-layer column c: v_B -> slots 0..2, u -> slots 10..13.
+int rtn::Model::in_col(int c) const {
+  if (input == RTN_INPUT_FULL) return c;
+  return c < 3 ? c : 10 + (c - 3);
+}
+
+std::vector<float> rtn::Model::expand(const float* user) const {
+  std::vector<float> out((size_t)n_params, 0.f);
+  int64_t uo = 0;
+  for (int l = 0; l <= L; ++l) {
+    const int64_t fo = layer_fan_out(l), fi = layer_fan_in(l);
+    const int64_t ufi = l == 0 ? user_desc.d_in : fi, ufo = l == L ? user_desc.d_out : fo;
+    for (int64_t r = 0; r < ufo; ++r)
+      for (int64_t c = 0; c < ufi; ++c) out[w_off[l] + r * fi + (l == 0 ? in_col((int)c) : c)] = user[uo + r * ufi + c];
+    uo += ufo * ufi;
+    for (int64_t r = 0; r < ufo; ++r) out[b_off[l] + r] = user[uo + r];
+    uo += ufo;
+  }
+  return out;
+}
+
+void rtn::Model::contract(const float* internal, float* user) const {
+  int64_t uo = 0;
+  for (int l = 0; l <= L; ++l) {
+    const int64_t fo = layer_fan_out(l), fi = layer_fan_in(l);
+    const int64_t ufi = l == 0 ? user_desc.d_in : fi, ufo = l == L ? user_desc.d_out : fo;
+    for (int64_t r = 0; r < ufo; ++r)
+      for (int64_t c = 0; c < ufi; ++c) user[uo + r * ufi + c] = internal[w_off[l] + r * fi + (l == 0 ? in_col((int)c) : c)];
+    uo += ufo * ufi;
+    for (int64_t r = 0; r < ufo; ++r) user[uo + r] = internal[b_off[l] + r];
+    uo += ufo;
+  }
+}
+
 rtn_status rtn::Model::init(const rtn_mlp_desc& d) {
   (void)num_cu();  // device query outside any stream capture
+  // the variants are stored embedded in the full 14-input / 6-output layout
+  // (zero columns and rows), so every network kernel sees the same shapes
+  user_desc = d;
+  input = d.input;
   desc = d;
+  desc.d_in = kDin;
+  desc.d_out = kDout;
   L = d.n_hidden;
   H = d.width;
-  n_params = count_params(d);
+  n_params = count_params(desc);
   int64_t off = 0;
   for (int l = 0; l <= L; ++l) {
     w_off[l] = off;
@@ -149,6 +200,7 @@ NetView rtn::Model::view(int prec) const {
   memset(&v, 0, sizeof v);
   v.L = L;
   v.act = desc.activation == RTN_ACT_SILU ? 0 : 1;
+  v.input = input;
   for (int l = 0; l <= L; ++l) {
     v.fw[l] = packed_fw[prec][l];
     v.bias[l] = params + b_off[l];
@@ -201,6 +253,7 @@ LatNet rtn::Model::lat_view() const {
   v.L = L;
   v.H = H;
   v.act = desc.activation == RTN_ACT_SILU ? 0 : 1;
+  v.input = input;
   for (int l = 0; l <= L; ++l) {
     v.W[l] = params + w_off[l];
     v.b[l] = params + b_off[l];
@@ -280,7 +333,8 @@ rtn_status rtn_model_create(const rtn_mlp_desc* desc, const float* params_host, 
     delete m;
     return s;
   }
-  hipError_t e = hipMemcpy(m->params, params_host, m->n_params * 4, hipMemcpyHostToDevice);
+  const std::vector<float> full = m->expand(params_host);
+  hipError_t e = hipMemcpy(m->params, full.data(), m->n_params * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete m;
     return hip_fail(e, "hipMemcpy(params)");
@@ -310,7 +364,8 @@ rtn_status rtn_model_set_params(rtn_model* model, const float* params_host) {
   if (!params_host) return fail(RTN_EINVAL, "params_host is NULL");
   Model* m = reinterpret_cast<Model*>(model);
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(m->params, params_host, m->n_params * 4, hipMemcpyHostToDevice));
+  const std::vector<float> full = m->expand(params_host);
+  HIP_TRY(hipMemcpy(m->params, full.data(), m->n_params * 4, hipMemcpyHostToDevice));
   rtn_status s = m->repack(nullptr);
   if (s) return s;
   HIP_TRY(hipStreamSynchronize(nullptr));
@@ -322,7 +377,9 @@ rtn_status rtn_model_get_params(rtn_model* model, float* params_host) {
   if (!params_host) return fail(RTN_EINVAL, "params_host is NULL");
   Model* m = reinterpret_cast<Model*>(model);
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(params_host, m->params, m->n_params * 4, hipMemcpyDeviceToHost));
+  std::vector<float> full((size_t)m->n_params);
+  HIP_TRY(hipMemcpy(full.data(), m->params, m->n_params * 4, hipMemcpyDeviceToHost));
+  m->contract(full.data(), params_host);
   return RTN_OK;
 }
 
@@ -449,7 +506,7 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
         if ((e = launch_lat_reverse(lv, n_nodes, static_cast<float*>(m->stash), lat_g, J, q)) != hipSuccess) return e;
       }
       ProfScope ps("rk4_linearize", q);
-      return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q);
+      return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q, m->input);
     }
     {
       ProfScope ps("mlp_forward_chain", q);
@@ -462,7 +519,7 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
       if ((e = launch_mlp_reverse(prec, m->H, v, n_nodes, m->stash, J, nullptr, q, tc.rev)) != hipSuccess) return e;
     }
     ProfScope ps("rk4_linearize", q);
-    return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q);
+    return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q, m->input);
   };
   // The three launches are captured once per distinct argument set into a HIP
   // graph (on a private stream) and replayed as one graph launch on the caller's
@@ -585,6 +642,7 @@ extern "C" rtn_status rtn_linearize_second(const rtn_model* model, int32_t prec,
   if (n_nodes == 0) return RTN_OK;
   if (!x || !u || !x_next || !A || !B) return fail(RTN_EINVAL, "x, u, x_next, A and B must be device pointers");
   Model* m = const_cast<Model*>(reinterpret_cast<const Model*>(model));
+  if ((s = full_only(m, "rtn_linearize_second"))) return s;
   hipStream_t st = (hipStream_t)stream;
   QuadConst qc{quad->mass, quad->Jx, quad->Jy, quad->Jz, quad->arm, quad->c_tau, quad->g};
   const LatNet lv = m->lat_view();
@@ -906,6 +964,7 @@ rtn_status rtn_mlp_forward(rtn_model* model, int32_t prec, int32_t batch, const 
   if (batch <= 0) return fail(RTN_EINVAL, "batch must be >= 1 (got %d)", batch);
   if (!in || !out) return fail(RTN_EINVAL, "in and out must be device pointers");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_mlp_forward")) return sv;
   hipStream_t st = (hipStream_t)stream;
   if ((s = train_forward(m, prec, batch, in, st))) return s;
   HIP_TRY(hipMemcpyAsync(out, m->ty, (size_t)batch * kDout * 4, hipMemcpyDeviceToDevice, st));
@@ -915,6 +974,7 @@ rtn_status rtn_mlp_forward(rtn_model* model, int32_t prec, int32_t batch, const 
 rtn_status rtn_mlp_backward(rtn_model* model, int32_t batch, const float* dout, float* din, void* stream) {
   if (!model) return fail(RTN_EINVAL, "model is NULL");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_mlp_backward")) return sv;
   if (m->tprec < 0 || m->tbatch != batch)
     return fail(RTN_EINVAL, "rtn_mlp_backward needs a preceding rtn_mlp_forward with the same batch (%d)", batch);
   if (!dout) return fail(RTN_EINVAL, "dout must be a device pointer");
@@ -924,6 +984,7 @@ rtn_status rtn_mlp_backward(rtn_model* model, int32_t batch, const float* dout, 
 rtn_status rtn_model_zero_grad(rtn_model* model, void* stream) {
   if (!model) return fail(RTN_EINVAL, "model is NULL");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_model_zero_grad")) return sv;
   HIP_TRY(hipMemsetAsync(m->grad, 0, m->n_params * 4, (hipStream_t)stream));
   return RTN_OK;
 }
@@ -931,6 +992,7 @@ rtn_status rtn_model_zero_grad(rtn_model* model, void* stream) {
 rtn_status rtn_model_get_grad(rtn_model* model, float* grad_host) {
   if (!model || !grad_host) return fail(RTN_EINVAL, "model and grad_host are required");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_model_get_grad")) return sv;
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(grad_host, m->grad, m->n_params * 4, hipMemcpyDeviceToHost));
   return RTN_OK;
@@ -940,6 +1002,7 @@ rtn_status rtn_adam_step(rtn_model* model, float lr, float beta1, float beta2, f
   if (!model) return fail(RTN_EINVAL, "model is NULL");
   rtn_status s = check_adam(lr, beta1, beta2, eps);
   if (s) return s;
+  if ((s = full_only(reinterpret_cast<Model*>(model), "rtn_adam_step"))) return s;
   return adam_update(reinterpret_cast<Model*>(model), lr, beta1, beta2, eps, (hipStream_t)stream);
 }
 
@@ -952,6 +1015,7 @@ rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch, const f
   if (batch <= 0) return fail(RTN_EINVAL, "batch must be >= 1 (got %d)", batch);
   if (!in || !target) return fail(RTN_EINVAL, "in and target must be device pointers");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_train_step")) return sv;
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipMemsetAsync(m->grad, 0, m->n_params * 4, st));
   if ((s = train_forward(m, prec, batch, in, st))) return s;
@@ -963,6 +1027,7 @@ rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch, const f
 rtn_status rtn_model_get_adam(rtn_model* model, float* m_host, float* v_host, int64_t* step) {
   if (!model) return fail(RTN_EINVAL, "model is NULL");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_model_get_adam")) return sv;
   HIP_TRY(hipDeviceSynchronize());
   if (m_host) HIP_TRY(hipMemcpy(m_host, m->adam_m, m->n_params * 4, hipMemcpyDeviceToHost));
   if (v_host) HIP_TRY(hipMemcpy(v_host, m->adam_v, m->n_params * 4, hipMemcpyDeviceToHost));
@@ -974,6 +1039,7 @@ rtn_status rtn_model_set_adam(rtn_model* model, const float* m_host, const float
   if (!model) return fail(RTN_EINVAL, "model is NULL");
   if (step < 0) return fail(RTN_EINVAL, "step must be >= 0");
   Model* m = reinterpret_cast<Model*>(model);
+  if (rtn_status sv = full_only(m, "rtn_model_set_adam")) return sv;
   HIP_TRY(hipDeviceSynchronize());
   if (m_host) HIP_TRY(hipMemcpy(m->adam_m, m_host, m->n_params * 4, hipMemcpyHostToDevice));
   if (v_host) HIP_TRY(hipMemcpy(m->adam_v, v_host, m->n_params * 4, hipMemcpyHostToDevice));
@@ -996,6 +1062,7 @@ extern "C" rtn_status rtn_linearize_exact(const rtn_model* model, int32_t prec, 
   if (n_nodes == 0) return RTN_OK;
   if (!x || !u || !x_next || !A || !B) return fail(RTN_EINVAL, "x, u, x_next, A and B must be device pointers");
   Model* m = const_cast<Model*>(reinterpret_cast<const Model*>(model));
+  if ((s = full_only(m, "rtn_linearize_exact"))) return s;
   if (prec == RTN_FP8 && !m->calibrated) return fail(RTN_EINVAL, "RTN_FP8 needs rtn_model_calibrate first");
   hipStream_t st = (hipStream_t)stream;
   if ((s = m->ensure_workspace(n_nodes, 0, st))) return s;

@@ -39,8 +39,8 @@ def test_version(lib):
     assert b"gfx950" in lib.rtn_version()
 
 
-def desc(L=2, W=64, act=0, d_in=14, d_out=6):
-    return MlpDesc(d_in, d_out, L, W, act)
+def desc(L=2, W=64, act=0, d_in=14, d_out=6, inp=0):
+    return MlpDesc(d_in, d_out, L, W, act, inp)
 
 
 def test_param_count(lib):
@@ -51,11 +51,19 @@ def test_param_count(lib):
     assert n.value == 798726
     assert lib.rtn_param_count(ctypes.byref(desc(5, 512)), ctypes.byref(n)) == RTN_OK
     assert n.value == 1061382
+    # the residual variants of Sec. VI count their own (smaller) first and last layers
+    assert lib.rtn_param_count(ctypes.byref(desc(2, 64, d_in=3, d_out=3, inp=1)), ctypes.byref(n)) == RTN_OK
+    assert n.value == 64 * 3 + 64 + 64 * 64 + 64 + 3 * 64 + 3
+    assert lib.rtn_param_count(ctypes.byref(desc(2, 64, d_in=7, d_out=3, inp=2)), ctypes.byref(n)) == RTN_OK
+    assert n.value == 64 * 7 + 64 + 64 * 64 + 64 + 3 * 64 + 3
 
 
 @pytest.mark.parametrize("d,code", [
     (desc(d_in=13), RTN_EINVAL), (desc(d_out=5), RTN_EINVAL), (desc(L=0), RTN_EINVAL),
-    (desc(L=17), RTN_EINVAL), (desc(act=7), RTN_EINVAL), (desc(W=96), RTN_ENOTSUP), (desc(W=0), RTN_EINVAL)])
+    (desc(L=17), RTN_EINVAL), (desc(act=7), RTN_EINVAL), (desc(W=96), RTN_ENOTSUP), (desc(W=0), RTN_EINVAL),
+    (desc(inp=3), RTN_EINVAL), (desc(inp=1), RTN_EINVAL), (desc(d_in=3, d_out=6, inp=1), RTN_EINVAL),
+    (desc(d_in=7, d_out=3, inp=1), RTN_EINVAL), (desc(d_in=3, d_out=3, inp=2), RTN_EINVAL),
+    (desc(d_in=3, d_out=3, inp=0), RTN_EINVAL)])
 def test_bad_descriptor(lib, d, code):
     n = ctypes.c_int64()
     assert lib.rtn_param_count(ctypes.byref(d), ctypes.byref(n)) == code

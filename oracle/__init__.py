@@ -23,6 +23,9 @@ RA-L 2023):
 * ``simulator``  drag-augmented synthetic plant and residual labels (Sec. VII,
                  system identification).
 * ``quant``      round-to-bf16 / round-to-e4m3 emulation.
+* ``double_integrator``  the runtime workload of Sec. V: double-integrator
+                 nominal model, its first-order RK4 linearisation and one
+                 real-time iteration (linearise, Riccati, rollout).
 
 Float64 throughout.  Inputs arrive as float32 arrays and are promoted exactly.
 """

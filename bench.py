@@ -255,6 +255,57 @@ def extras(torch, rtn, lin_out, off, stream):
     return res
 
 
+# The paper's control frequencies of its own implementation on an RTX 3000 laptop GPU
+# (Sec. V): the two-layer width sweep (read from the plotted data) and Table II.
+PAPER_RTX3000_HZ_TWO_LAYER = {2: 783.8, 4: 763.0, 8: 767.3, 16: 776.7, 32: 773.8, 64: 763.7, 128: 756.3,
+                              256: 770.5, 512: 758.6, 1024: 737.8, 2048: 704.6, 4096: 500.9, 8192: 169.7}
+PAPER_RTX3000_HZ_TABLE_II = {(2, 16): 781, (2, 128): 770, (5, 16): 586, (5, 128): 598, (12, 32): 363,
+                             (12, 512): 363, (20, 512): 232, (50, 512): 117}
+
+
+def di_runtime(torch, rtn, stream):
+    """The runtime workload of Sec. V: one real-time iteration (network value and
+    Jacobian, RK4 linearisation, Riccati recursion, rollout) of the double integrator
+    with N = 10 nodes per call, for the two-layer width sweep and the networks of
+    Table II.  The output layer is zero, as in the paper's runs; all work is done."""
+    from workload import xavier_params as xp
+    N, dt = 10, 0.05
+    Q, R, QN = np.eye(2), np.array([0.1]), np.eye(2)
+    g = np.random.default_rng(0)
+    x = torch.from_numpy(g.normal(0, 1, (N, 2)).astype(np.float32)).cuda()
+    u = torch.from_numpy(g.normal(0, 1, N).astype(np.float32)).cuda()
+    xN = torch.from_numpy(g.normal(0, 1, (1, 2)).astype(np.float32)).cuda()
+    x0 = torch.from_numpy(g.normal(0, 1, (1, 2)).astype(np.float32)).cuda()
+
+    def tick_time(L, H):
+        m = None
+        if L:
+            Ws, bs = xp(L, H, seed=H, d_in=2, d_out=2)
+            Ws[-1][:] = 0.0
+            m = rtn.DiModel(Ws, bs)
+        out = {}
+        f = lambda: rtn.di_rti(x, u, xN, x0, m, Q, R, QN, dt, out=out, stream=stream)
+        ms, wall = time_steps(torch, f, 200, 20, stream)
+        if m is not None:
+            m.close()
+        return ms, wall
+
+    res = {"nodes": N, "nominal_only": None, "two_layer": {}, "table_ii": {}}
+    ms, wall = tick_time(0, 0)
+    res["nominal_only"] = {"us_per_iteration": ms * 1e3, "hz": 1e3 / ms, "host_us_per_call": wall * 1e3}
+    for H in sorted(PAPER_RTX3000_HZ_TWO_LAYER):
+        ms, wall = tick_time(2, H)
+        wbytes = 4.0 * (3 * H + H * H + H + 2 * H + 2)
+        res["two_layer"][H] = {"us_per_iteration": ms * 1e3, "hz": 1e3 / ms, "host_us_per_call": wall * 1e3,
+                               "weight_GBps": wbytes / (ms * 1e-3) / 1e9,
+                               "paper_rtx3000_hz": PAPER_RTX3000_HZ_TWO_LAYER[H]}
+    for (L, H), hz in PAPER_RTX3000_HZ_TABLE_II.items():
+        ms, wall = tick_time(L, H)
+        res["table_ii"][f"{L}x{H}"] = {"us_per_iteration": ms * 1e3, "hz": 1e3 / ms, "host_us_per_call": wall * 1e3,
+                                       "paper_rtx3000_hz": hz}
+    return res
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -347,6 +398,7 @@ def main():
         result["other_precisions_same_workload"] = cmp
     if not args.no_extras:
         result["extras"] = extras(torch, rtn, out, off, stream)
+        result["extras"]["double_integrator_rti"] = di_runtime(torch, rtn, stream)
     if not args.no_cpu:
         ric = rtn.riccati(out["A"], out["B"], np.eye(13), 0.1 * np.eye(4), np.eye(13), offsets=off, stream=stream)
         torch.cuda.synchronize()

@@ -320,6 +320,62 @@ rtn_status rtn_tune_set(int32_t prec, int32_t width, int32_t n_hidden, int32_t n
 rtn_status rtn_tune_save(const char* path);
 rtn_status rtn_tune_load(const char* path);
 
+/* ---------------------------------------------------------------------------
+ * Runtime workload of Sec. V: a double integrator x = [p, pdot], nominal
+ * model f_F(x, u) = [pdot, u] (scalar input u), with a residual network f_D
+ * from the state (2 values) to 2 values added to x-dot: n_hidden layers of
+ * `width` units (the paper's runtime study sweeps two layers of 2..8192 units
+ * and its Table II lists deeper ones; the 2-in / 2-out shape is the one its
+ * parameter counts imply).  The paper sets the output layer to zero; any
+ * weights work.
+ *
+ * Parameters (host fp32, flat): W_1 [width][2], b_1 [width], then for each
+ * further hidden layer W_l [width][width], b_l [width], then W_out [2][width],
+ * b_out [2].  1 <= n_hidden <= 64, 1 <= width <= 8192, activation as
+ * rtn_activation.  The model keeps its own fp32 copy on the current device;
+ * every call below runs on the device the model was created on.  Calls on one
+ * model are not thread-safe (they share its workspace). */
+typedef struct rtn_di_model rtn_di_model;
+
+rtn_status rtn_di_param_count(int32_t n_hidden, int32_t width, int64_t* count);
+rtn_status rtn_di_model_create(int32_t n_hidden, int32_t width, int32_t activation, const float* params_host,
+                               rtn_di_model** out);
+rtn_status rtn_di_model_destroy(rtn_di_model* model);
+
+/* Preparation phase of Sec. IV-B for the double integrator: the network value
+ * f_D-bar and Jacobian J_D at every node (by forward-mode tangents through the
+ * layers), and one RK4 step (Sec. III) of f_F plus the first-order local
+ * approximation eq. (4) held fixed, with its exact sensitivities (eq. (2)).
+ *   model   nullable: NULL gives the nominal model alone (f_D = 0)
+ *   dt      > 0;  n_nodes >= 0 (0 does nothing)
+ *   x [n][2], u [n] (device fp32) -> x_next [n][2], A [n][2][2] (row-major,
+ *   A[k][i][j] = d x_{k+1,i} / d x_{k,j}), B [n][2] = d x_{k+1} / d u_k;
+ *   f_D [n][2], J_D [n][2][2] nullable (device fp32). */
+rtn_status rtn_di_linearize(const rtn_di_model* model, float dt, int32_t n_nodes, const float* x, const float* u,
+                            float* x_next, float* A, float* B, float* f_D, float* J_D, void* stream);
+
+/* One real-time iteration (Sec. IV-B) of every instance: linearise at the
+ * iterate, then solve the QP of Sec. IV-A (continuity eq. (2), no inequality
+ * rows) with the Gauss-Newton tracking cost
+ *   sum_k 1/2 |x_k - x_ref|_Q^2 + 1/2 R u_k^2 + 1/2 |x_N - x_ref|_QN^2
+ * by the fp64 Riccati recursion and the rollout from dx_0 = x0 - x_0.
+ *   model  nullable, as for rtn_di_linearize
+ *   n_inst, offsets_host, n_nodes  as for rtn_linearize; every instance has at
+ *          most 512 nodes
+ *   Q_host [2][2], R_host [1], QN_host [2][2]  host fp64, finite, R > 0
+ *   x [n][2], u [n]   iterate states x_0..x_{N-1} and inputs of each instance's
+ *                     nodes (device fp32); xN [n_inst][2] terminal states;
+ *                     x0 [n_inst][2] measured states; x_ref nullable
+ *                     [n_inst][2] (zero when NULL)
+ * outputs (device fp64): du [n], dx [n][2] (dx_0..dx_{N-1}), dxN [n_inst][2];
+ *   gaps c_k = x_next_k - x_{k+1} (x_N for the last node).  A [n][2][2],
+ *   B [n][2], x_next [n][2] nullable (device fp32): the linearisation used.
+ * Repeated calls with the same arguments replay a captured HIP graph. */
+rtn_status rtn_di_rti(const rtn_di_model* model, float dt, int32_t n_inst, const int32_t* offsets_host,
+                      int32_t n_nodes, const double* Q_host, const double* R_host, const double* QN_host,
+                      const float* x, const float* u, const float* xN, const float* x0, const float* x_ref,
+                      double* du, double* dx, double* dxN, float* A, float* B, float* x_next, void* stream);
+
 /* Kernel timing (tracing).  When enabled, every kernel the library launches is
  * bracketed by a pair of HIP events recorded on the call's stream (a few
  * microseconds of overhead per launch; leave it off for production timing).

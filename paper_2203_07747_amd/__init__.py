@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, INPUT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "DiModel", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -472,3 +472,101 @@ def mlp_function():
             return ctx.model.backward_batch(dy.contiguous(), want_din=True), None, None
 
     return MLP
+
+
+# ---- runtime workload of Sec. V: double integrator with a network residual ------------
+class DiModel:
+    """A 2-in / 2-out residual network of the double-integrator workload (fp32 on the GPU)."""
+
+    def __init__(self, Ws: Sequence[np.ndarray], bs: Sequence[np.ndarray], activation: str = "silu"):
+        L = len(Ws) - 1
+        width = Ws[0].shape[0]
+        flat = Model._flatten(Ws, bs)
+        n = ctypes.c_int64()
+        check(load().rtn_di_param_count(L, width, ctypes.byref(n)), "rtn_di_param_count")
+        if n.value != flat.size:
+            raise ValueError(f"parameter count {flat.size} does not match n_hidden={L}, width={width} ({n.value})")
+        h = ctypes.c_void_p()
+        check(load().rtn_di_model_create(L, width, ACT[activation], flat.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(h)), "rtn_di_model_create")
+        self._h = h
+        self.n_hidden, self.width, self.n_params = L, width, n.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("model has been closed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            load().rtn_di_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def di_linearize(x, u, model: Optional[DiModel] = None, dt: float = 0.05, want_fd: bool = True,
+                 stream=None) -> Dict[str, object]:
+    """rtn_di_linearize over device tensors x [n,2], u [n] (fp32): x_next [n,2], A [n,2,2],
+    B [n,2] and, on request, f_D [n,2], J_D [n,2,2]."""
+    torch = _torch()
+    n = x.shape[0]
+    f32 = torch.float32
+    out = {k: torch.empty(s, dtype=f32, device=x.device)
+           for k, s in (("x_next", (n, 2)), ("A", (n, 2, 2)), ("B", (n, 2)))}
+    if want_fd:
+        out["f_D"] = torch.empty((n, 2), dtype=f32, device=x.device)
+        out["J_D"] = torch.empty((n, 2, 2), dtype=f32, device=x.device)
+    check(load().rtn_di_linearize(model.handle if model is not None else None, ctypes.c_float(dt), n,
+                                  _dev(x, f32, (n, 2), "x"), _dev(u, f32, (n,), "u"),
+                                  _dev(out["x_next"], f32, (n, 2), "x_next"), _dev(out["A"], f32, (n, 2, 2), "A"),
+                                  _dev(out["B"], f32, (n, 2), "B"),
+                                  _dev(out.get("f_D"), f32, (n, 2), "f_D"), _dev(out.get("J_D"), f32, (n, 2, 2), "J_D"),
+                                  _stream(stream)), "rtn_di_linearize")
+    return out
+
+
+def di_rti(x, u, xN, x0, model: Optional[DiModel], Q, R, QN, dt: float = 0.05, offsets=None, x_ref=None,
+           want_linearisation: bool = False, out: Optional[Dict[str, object]] = None,
+           stream=None) -> Dict[str, object]:
+    """rtn_di_rti: one real-time iteration of every instance.  x [n,2], u [n], xN, x0 (and
+    x_ref) [n_inst,2] device fp32; Q, R, QN host fp64.  Returns du [n], dx [n,2],
+    dxN [n_inst,2] (fp64) and, on request, the linearisation A, B, x_next (fp32)."""
+    torch = _torch()
+    n = x.shape[0]
+    if offsets is None:
+        n_inst, off_ptr = 1, None
+    else:
+        off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst, off_ptr = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+    if out is None:
+        out = {}
+    dev = x.device
+    f32, f64 = torch.float32, torch.float64
+
+    def get(name, shape, dtype):
+        t = out.get(name)
+        if t is None:
+            t = out[name] = torch.empty(shape, dtype=dtype, device=dev)
+        return t
+    du, dx, dxN = get("du", (n,), f64), get("dx", (n, 2), f64), get("dxN", (n_inst, 2), f64)
+    A = get("A", (n, 2, 2), f32) if want_linearisation else None
+    B = get("B", (n, 2), f32) if want_linearisation else None
+    xn = get("x_next", (n, 2), f32) if want_linearisation else None
+    Qh = np.ascontiguousarray(Q, dtype=np.float64).reshape(2, 2)
+    Rh = np.ascontiguousarray(R, dtype=np.float64).reshape(1)
+    QNh = np.ascontiguousarray(QN, dtype=np.float64).reshape(2, 2)
+    check(load().rtn_di_rti(model.handle if model is not None else None, ctypes.c_float(dt), n_inst, off_ptr, n,
+                            Qh.ctypes.data_as(ctypes.c_void_p), Rh.ctypes.data_as(ctypes.c_void_p),
+                            QNh.ctypes.data_as(ctypes.c_void_p),
+                            _dev(x, f32, (n, 2), "x"), _dev(u, f32, (n,), "u"), _dev(xN, f32, (n_inst, 2), "xN"),
+                            _dev(x0, f32, (n_inst, 2), "x0"), _dev(x_ref, f32, (n_inst, 2), "x_ref"),
+                            _dev(du, f64, (n,), "du"), _dev(dx, f64, (n, 2), "dx"), _dev(dxN, f64, (n_inst, 2), "dxN"),
+                            _dev(A, f32, (n, 2, 2), "A"), _dev(B, f32, (n, 2), "B"), _dev(xn, f32, (n, 2), "x_next"),
+                            _stream(stream)), "rtn_di_rti")
+    return out

@@ -61,6 +61,14 @@ SIGNATURES = {
                                   c_void_p, c_void_p]),
     "rtn_lq_rollout": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "rtn_di_param_count": (c_int32, [c_int32, c_int32, P(c_int64)]),
+    "rtn_di_model_create": (c_int32, [c_int32, c_int32, c_int32, c_void_p, P(c_void_p)]),
+    "rtn_di_model_destroy": (c_int32, [c_void_p]),
+    "rtn_di_linearize": (c_int32, [c_void_p, c_float, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p]),
+    "rtn_di_rti": (c_int32, [c_void_p, c_float, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_void_p, c_void_p, c_void_p]),
     "rtn_tune_mode": (c_int32, [c_int32]),
     "rtn_tune_get": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "rtn_tune_set": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p]),

@@ -1,0 +1,36 @@
+// Kernels of the double-integrator runtime workload (Sec. V): a 2-input,
+// 2-output residual network of any width, evaluated with its Jacobian by
+// forward-mode tangents in the same weight sweep, and one real-time iteration
+// (RK4 linearisation, Riccati recursion, rollout) per instance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtn {
+
+constexpr int kDiMaxHidden = 64;
+constexpr int kDiMaxWidth = 8192;
+constexpr int kDiMaxHorizon = 512;  // nodes per instance in one real-time iteration
+
+// Activations of a node batch: three rows per node, [value h_l; dh_l/dp; dh_l/dv],
+// row-major [3n][width].
+hipError_t launch_di_first_layer(int n, int H, const float* W, const float* b, int act, const float* x, float* Z,
+                                 hipStream_t st);
+hipError_t launch_di_hidden_layer(int n, int K, int N, const float* Zin, const float* W, const float* b, int act,
+                                  float* Zout, hipStream_t st);
+hipError_t launch_di_output_layer(int n, int K, const float* W, const float* b, const float* Z, float* y, float* J,
+                                  hipStream_t st);
+// Per node RK4 step of the nominal model plus the affine residual (y, J nullable = 0).
+hipError_t launch_di_linearize(int n, float dt, const float* x, const float* u, const float* y, const float* J,
+                               float* xn, float* A, float* B, hipStream_t st);
+
+struct DiCost {
+  double Q[4], R, QN[4];
+};
+// One real-time iteration per instance (one workgroup each); A, B, xn nullable.
+hipError_t launch_di_rti(int n_inst, const int* offsets, float dt, const DiCost& cost, const float* x, const float* u,
+                         const float* xN, const float* x0, const float* xref, const float* y, const float* J,
+                         double* du, double* dx, double* dxN, float* A, float* B, float* xn, hipStream_t st);
+
+}  // namespace rtn

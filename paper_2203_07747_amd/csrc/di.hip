@@ -1,0 +1,378 @@
+// Double-integrator runtime workload (Sec. V).
+//
+// Nominal model x = [p, pdot], f_F(x, u) = [pdot, u]; residual f_D: a network
+// from the state (2 values) to 2 values with n_hidden layers of any width up
+// to 8192.  The Jacobian J_D (2 x 2) is carried forward: each node owns three
+// activation rows, the value h_l and its derivatives along p and pdot,
+//   h_1 = act(W_1 x + b_1),   T_1 = act'(a_1) (.) W_1
+//   h_l = act(W_l h_{l-1} + b_l),   T_l = act'(a_l) (.) (W_l T_{l-1})
+//   y = W_{L+1} h_L + b_{L+1},   J_D = W_{L+1} T_L,
+// so one sweep over each weight matrix gives value and Jacobian (reverse mode
+// would read every matrix twice; with two inputs the tangent rows cost less
+// than the second read).  For wide layers the sweep streams the weights from
+// HBM once and is bound by that; the rows of all nodes share each weight load.
+//
+// Then the first-order local approximation (eq. (4)) is held fixed in one RK4
+// step (Sec. III) to give x_{k+1}, A_k, B_k (eq. (2)), and one real-time
+// iteration solves the LQ subproblem by the Riccati recursion and a rollout.
+#include "common.h"
+#include "di.h"
+
+namespace rtn {
+
+namespace {
+
+constexpr int kNodesPerTile = 10;  // 30 of the 32 rows of an MFMA tile
+constexpr int kTileRows = 3 * kNodesPerTile;
+constexpr int kMaxWaves = 16;
+
+__device__ inline float di_act(float a, int act, float* dact) {
+  if (act == 0) {
+    const float s = 1.f / (1.f + __expf(-a));
+    *dact = s * (1.f + a * (1.f - s));
+    return a * s;
+  }
+  *dact = 1.f;
+  return a;
+}
+
+__global__ void __launch_bounds__(256) di_first_layer(int n, int H, const float* __restrict__ W,
+                                                      const float* __restrict__ b, int act,
+                                                      const float* __restrict__ x, float* __restrict__ Z) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)n * H) return;
+  const int i = (int)(idx / H), c = (int)(idx % H);
+  const float w0 = W[2 * c], w1 = W[2 * c + 1];
+  float d;
+  const float h = di_act(fmaf(w0, x[2 * i], fmaf(w1, x[2 * i + 1], b[c])), act, &d);
+  float* z = Z + (size_t)3 * i * H + c;
+  z[0] = h;
+  z[H] = d * w0;
+  z[2 * (size_t)H] = d * w1;
+}
+
+// Zout = epilogue(Zin W^T) for W [N][K] row-major; one workgroup per 32 output
+// columns and 10 nodes, its waves splitting K.  MFMA 32x32x2 fp32: lane l
+// supplies row (or column) l % 32 and, for the 4 products of one group of 8
+// K-values, k = 8 j + 4 (l / 32) + t; both operands are read as float4 along K
+// (VEC, K % 8 == 0) or element by element (small odd widths).
+template <bool VEC>
+__global__ void __launch_bounds__(kMaxWaves * kWave)
+di_hidden_layer(int n, int K, int N, const float* __restrict__ Zin, const float* __restrict__ W,
+                const float* __restrict__ b, int act, float* __restrict__ Zout) {
+  __shared__ float part[kMaxWaves][kTileRows * 33];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int c0 = blockIdx.x * 32, node0 = blockIdx.y * kNodesPerTile;
+  const int rows = 3 * min(kNodesPerTile, n - node0);
+  const int r = lane & 31, h = lane >> 5;
+  const bool rv = r < rows, cv = c0 + r < N;
+  const float* za = Zin + ((size_t)node0 * 3 + (rv ? r : 0)) * K;
+  const float* wb = W + (size_t)(cv ? c0 + r : 0) * K;
+  const int groups = (K + 7) / 8;
+  f32x16 acc = {};
+  if constexpr (VEC) {
+    constexpr int U = 4;  // groups in flight per wave
+    int j = wave;
+    for (; j + (U - 1) * nw < groups; j += U * nw) {
+      float4 av[U], bv[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int k = 8 * (j + q * nw) + 4 * h;
+        av[q] = rv ? *reinterpret_cast<const float4*>(za + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+        bv[q] = cv ? *reinterpret_cast<const float4*>(wb + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].x, bv[q].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].y, bv[q].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].z, bv[q].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].w, bv[q].w, acc, 0, 0, 0);
+      }
+    }
+    for (; j < groups; j += nw) {
+      const int k = 8 * j + 4 * h;
+      const float4 a4 = rv ? *reinterpret_cast<const float4*>(za + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 b4 = cv ? *reinterpret_cast<const float4*>(wb + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
+    }
+  } else {
+    for (int j = wave; j < groups; j += nw) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 8 * j + 4 * h + t;
+        const float a = (rv && k < K) ? za[k] : 0.f;
+        const float bb = (cv && k < K) ? wb[k] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
+      }
+    }
+  }
+  // accumulator register i of lane l: row (i/4)*8 + (l/32)*4 + i%4, column l%32
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = (i >> 2) * 8 + h * 4 + (i & 3);
+    if (row < kTileRows) part[wave][row * 33 + r] = acc[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNodesPerTile * 32; e += blockDim.x) {
+    const int q = e >> 5, cc = e & 31, node = node0 + q, col = c0 + cc;
+    if (3 * q >= rows || col >= N) continue;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int w = 0; w < nw; ++w) {
+      s0 += part[w][(3 * q) * 33 + cc];
+      s1 += part[w][(3 * q + 1) * 33 + cc];
+      s2 += part[w][(3 * q + 2) * 33 + cc];
+    }
+    float d;
+    const float hv = di_act(s0 + b[col], act, &d);
+    float* zo = Zout + (size_t)3 * node * N + col;
+    zo[0] = hv;
+    zo[N] = d * s1;
+    zo[2 * (size_t)N] = d * s2;
+  }
+}
+
+// y[i][j] = W[j] . h + b[j], J[i][j][m] = W[j] . T_m: one workgroup per (node, output).
+__global__ void __launch_bounds__(256) di_output_layer(int n, int K, const float* __restrict__ W,
+                                                       const float* __restrict__ b, const float* __restrict__ Z,
+                                                       float* __restrict__ y, float* __restrict__ J) {
+  __shared__ float red[3][4];
+  const int i = blockIdx.x >> 1, j = blockIdx.x & 1, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const float* w = W + (size_t)j * K;
+  const float* z = Z + (size_t)3 * i * K;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int k = t; k < K; k += 256) {
+    const float wk = w[k];
+    s0 = fmaf(wk, z[k], s0);
+    s1 = fmaf(wk, z[K + k], s1);
+    s2 = fmaf(wk, z[2 * (size_t)K + k], s2);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off);
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+  }
+  if (lane == 0) {
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+    red[2][wave] = s2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    y[2 * i + j] = red[0][0] + red[0][1] + red[0][2] + red[0][3] + b[j];
+    J[(2 * i + j) * 2 + 0] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    J[(2 * i + j) * 2 + 1] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  }
+  (void)n;
+}
+
+// One RK4 step of F(xi) = [xi_1, u] + y + J (xi - x) with the tangent
+// S = d xi / d [x, u] (2 x 3) carried through the stages.
+__device__ inline void di_rk4(const float x[2], float u, const float y[2], const float J[4], float dt, float xn[2],
+                              float A[4], float B[2]) {
+  const float cst[4] = {0.f, 0.5f, 0.5f, 1.f};
+  const float wst[4] = {1.f, 2.f, 2.f, 1.f};
+  // M = df_F/dx + J
+  const float M00 = J[0], M01 = 1.f + J[1], M10 = J[2], M11 = J[3];
+  float k0 = 0.f, k1 = 0.f, xa0 = 0.f, xa1 = 0.f;
+  float dk[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}}, Sa[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float cdt = cst[s] * dt;
+    const float d0 = cdt * k0, d1 = cdt * k1;  // x_s - x
+    float S[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      S[0][c] = (c == 0 ? 1.f : 0.f) + cdt * dk[0][c];
+      S[1][c] = (c == 1 ? 1.f : 0.f) + cdt * dk[1][c];
+    }
+    k0 = (x[1] + d1) + y[0] + J[0] * d0 + J[1] * d1;
+    k1 = u + y[1] + J[2] * d0 + J[3] * d1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dk[0][c] = M00 * S[0][c] + M01 * S[1][c];
+      dk[1][c] = M10 * S[0][c] + M11 * S[1][c] + (c == 2 ? 1.f : 0.f);
+    }
+    xa0 += wst[s] * k0;
+    xa1 += wst[s] * k1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Sa[0][c] += wst[s] * dk[0][c];
+      Sa[1][c] += wst[s] * dk[1][c];
+    }
+  }
+  const float dt6 = dt / 6.f;
+  xn[0] = x[0] + dt6 * xa0;
+  xn[1] = x[1] + dt6 * xa1;
+  A[0] = 1.f + dt6 * Sa[0][0];
+  A[1] = dt6 * Sa[0][1];
+  A[2] = dt6 * Sa[1][0];
+  A[3] = 1.f + dt6 * Sa[1][1];
+  B[0] = dt6 * Sa[0][2];
+  B[1] = dt6 * Sa[1][2];
+}
+
+__device__ inline void di_node(int node, float dt, const float* x, const float* u, const float* y, const float* J,
+                               float xn[2], float A[4], float B[2]) {
+  const float xk[2] = {x[2 * node], x[2 * node + 1]};
+  const float yk[2] = {y ? y[2 * node] : 0.f, y ? y[2 * node + 1] : 0.f};
+  float Jk[4] = {0.f, 0.f, 0.f, 0.f};
+  if (J)
+    for (int i = 0; i < 4; ++i) Jk[i] = J[4 * node + i];
+  di_rk4(xk, u[node], yk, Jk, dt, xn, A, B);
+}
+
+__global__ void __launch_bounds__(256) di_linearize_kernel(int n, float dt, const float* __restrict__ x,
+                                                           const float* __restrict__ u, const float* __restrict__ y,
+                                                           const float* __restrict__ J, float* __restrict__ xn,
+                                                           float* __restrict__ A, float* __restrict__ B) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= n) return;
+  float xo[2], Ao[4], Bo[2];
+  di_node(node, dt, x, u, y, J, xo, Ao, Bo);
+  for (int i = 0; i < 2; ++i) xn[2 * node + i] = xo[i];
+  for (int i = 0; i < 4; ++i) A[4 * node + i] = Ao[i];
+  for (int i = 0; i < 2; ++i) B[2 * node + i] = Bo[i];
+}
+
+// Per node LQ data in LDS (fp64): A 4 | B 2 | c 2 | q 2 | r 1 | K 2 | kff 1.
+constexpr int kLqStride = 14;
+
+// One instance per workgroup: the RK4 linearisation of its nodes (parallel),
+// then the Riccati recursion and the rollout (sequential in k, one lane):
+//   Quu = R + B^T P B,  Qux = B^T P A,  g = P c + p,  qx = q + A^T g,  qu = r + B^T g
+//   K = -Qux / Quu,  kff = -qu / Quu,  P <- sym(Q + A^T P A + Qux^T K),  p <- qx + Qux^T kff
+//   du_k = K dx_k + kff,  dx_{k+1} = A dx_k + B du_k + c_k,  dx_0 = x0 - x_0.
+__global__ void __launch_bounds__(64) di_rti_kernel(const int* __restrict__ offsets, float dt, DiCost cost,
+                                                    const float* __restrict__ x, const float* __restrict__ u,
+                                                    const float* __restrict__ xN, const float* __restrict__ x0,
+                                                    const float* __restrict__ xref, const float* __restrict__ y,
+                                                    const float* __restrict__ J, double* __restrict__ du,
+                                                    double* __restrict__ dx, double* __restrict__ dxN,
+                                                    float* __restrict__ Aout, float* __restrict__ Bout,
+                                                    float* __restrict__ xnout) {
+  __shared__ double sm[kDiMaxHorizon * kLqStride];
+  const int inst = blockIdx.x, t = threadIdx.x;
+  const int k0 = offsets[inst], N = offsets[inst + 1] - k0;
+  const double xr0 = xref ? xref[2 * inst] : 0.0, xr1 = xref ? xref[2 * inst + 1] : 0.0;
+  for (int k = t; k < N; k += 64) {
+    const int node = k0 + k;
+    float xo[2], Ao[4], Bo[2];
+    di_node(node, dt, x, u, y, J, xo, Ao, Bo);
+    if (xnout)
+      for (int i = 0; i < 2; ++i) xnout[2 * node + i] = xo[i];
+    if (Aout)
+      for (int i = 0; i < 4; ++i) Aout[4 * node + i] = Ao[i];
+    if (Bout)
+      for (int i = 0; i < 2; ++i) Bout[2 * node + i] = Bo[i];
+    const float* succ = k + 1 < N ? x + 2 * (node + 1) : xN + 2 * inst;
+    double* s = sm + k * kLqStride;
+    for (int i = 0; i < 4; ++i) s[i] = Ao[i];
+    s[4] = Bo[0];
+    s[5] = Bo[1];
+    s[6] = (double)xo[0] - (double)succ[0];
+    s[7] = (double)xo[1] - (double)succ[1];
+    const double e0 = (double)x[2 * node] - xr0, e1 = (double)x[2 * node + 1] - xr1;
+    s[8] = cost.Q[0] * e0 + cost.Q[1] * e1;
+    s[9] = cost.Q[2] * e0 + cost.Q[3] * e1;
+    s[10] = cost.R * (double)u[node];
+  }
+  __syncthreads();
+  if (t != 0) return;
+  const double* Q = cost.Q;
+  double P00 = cost.QN[0], P01 = cost.QN[1], P10 = cost.QN[2], P11 = cost.QN[3];
+  const double eN0 = (double)xN[2 * inst] - xr0, eN1 = (double)xN[2 * inst + 1] - xr1;
+  double p0 = P00 * eN0 + P01 * eN1, p1 = P10 * eN0 + P11 * eN1;
+  for (int k = N - 1; k >= 0; --k) {
+    double* s = sm + k * kLqStride;
+    const double A00 = s[0], A01 = s[1], A10 = s[2], A11 = s[3], B0 = s[4], B1 = s[5];
+    const double PB0 = P00 * B0 + P01 * B1, PB1 = P10 * B0 + P11 * B1;  // P B
+    const double Quu = cost.R + B0 * PB0 + B1 * PB1;
+    // Qux = B^T P A = (P^T B)^T A; P is kept symmetric
+    const double Qux0 = PB0 * A00 + PB1 * A10, Qux1 = PB0 * A01 + PB1 * A11;
+    const double g0 = P00 * s[6] + P01 * s[7] + p0, g1 = P10 * s[6] + P11 * s[7] + p1;
+    const double qx0 = s[8] + A00 * g0 + A10 * g1, qx1 = s[9] + A01 * g0 + A11 * g1;
+    const double qu = s[10] + B0 * g0 + B1 * g1;
+    const double K0 = -Qux0 / Quu, K1 = -Qux1 / Quu, kf = -qu / Quu;
+    // A^T P A
+    const double PA00 = P00 * A00 + P01 * A10, PA01 = P00 * A01 + P01 * A11;
+    const double PA10 = P10 * A00 + P11 * A10, PA11 = P10 * A01 + P11 * A11;
+    const double X00 = Q[0] + A00 * PA00 + A10 * PA10 + Qux0 * K0;
+    const double X01 = Q[1] + A00 * PA01 + A10 * PA11 + Qux0 * K1;
+    const double X10 = Q[2] + A01 * PA00 + A11 * PA10 + Qux1 * K0;
+    const double X11 = Q[3] + A01 * PA01 + A11 * PA11 + Qux1 * K1;
+    P00 = X00;
+    P11 = X11;
+    P01 = P10 = 0.5 * (X01 + X10);
+    p0 = qx0 + Qux0 * kf;
+    p1 = qx1 + Qux1 * kf;
+    s[11] = K0;
+    s[12] = K1;
+    s[13] = kf;
+  }
+  double d0 = (double)x0[2 * inst] - (double)x[2 * k0], d1 = (double)x0[2 * inst + 1] - (double)x[2 * k0 + 1];
+  for (int k = 0; k < N; ++k) {
+    const double* s = sm + k * kLqStride;
+    const double v = s[11] * d0 + s[12] * d1 + s[13];
+    du[k0 + k] = v;
+    dx[2 * (k0 + k)] = d0;
+    dx[2 * (k0 + k) + 1] = d1;
+    const double n0 = s[0] * d0 + s[1] * d1 + s[4] * v + s[6];
+    const double n1 = s[2] * d0 + s[3] * d1 + s[5] * v + s[7];
+    d0 = n0;
+    d1 = n1;
+  }
+  dxN[2 * inst] = d0;
+  dxN[2 * inst + 1] = d1;
+}
+
+}  // namespace
+
+hipError_t launch_di_first_layer(int n, int H, const float* W, const float* b, int act, const float* x, float* Z,
+                                 hipStream_t st) {
+  const long total = (long)n * H;
+  if (total <= 0) return hipSuccess;
+  di_first_layer<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(n, H, W, b, act, x, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_di_hidden_layer(int n, int K, int N, const float* Zin, const float* W, const float* b, int act,
+                                  float* Zout, hipStream_t st) {
+  if (n <= 0 || N <= 0) return hipSuccess;
+  const int groups = (K + 7) / 8;
+  int nw = groups / 8;  // about eight groups of eight K-values per wave
+  if (nw > kMaxWaves) nw = kMaxWaves;
+  if (nw < 1) nw = 1;
+  dim3 grid((N + 31) / 32, (n + kNodesPerTile - 1) / kNodesPerTile);
+  if (K % 8 == 0)
+    di_hidden_layer<true><<<grid, nw * kWave, 0, st>>>(n, K, N, Zin, W, b, act, Zout);
+  else
+    di_hidden_layer<false><<<grid, nw * kWave, 0, st>>>(n, K, N, Zin, W, b, act, Zout);
+  return hipGetLastError();
+}
+
+hipError_t launch_di_output_layer(int n, int K, const float* W, const float* b, const float* Z, float* y, float* J,
+                                  hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  di_output_layer<<<2 * n, 256, 0, st>>>(n, K, W, b, Z, y, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_di_linearize(int n, float dt, const float* x, const float* u, const float* y, const float* J,
+                               float* xn, float* A, float* B, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  di_linearize_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, dt, x, u, y, J, xn, A, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_di_rti(int n_inst, const int* offsets, float dt, const DiCost& cost, const float* x, const float* u,
+                         const float* xN, const float* x0, const float* xref, const float* y, const float* J,
+                         double* du, double* dx, double* dxN, float* A, float* B, float* xn, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  di_rti_kernel<<<n_inst, 64, 0, st>>>(offsets, dt, cost, x, u, xN, x0, xref, y, J, du, dx, dxN, A, B, xn);
+  return hipGetLastError();
+}
+
+}  // namespace rtn

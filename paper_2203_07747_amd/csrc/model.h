@@ -86,6 +86,7 @@ struct Model {
 };
 
 rtn_status hip_fail(hipError_t e, const char* what);
+rtn_status failf(rtn_status code, const char* fmt, ...);  // set the thread's error message, return code
 rtn_status inval(const char* fmt, const char* arg);
 rtn_status check_offsets(int32_t n_inst, const int32_t* offsets, int32_t n_nodes);
 

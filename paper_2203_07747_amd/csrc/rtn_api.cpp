@@ -34,6 +34,16 @@ rtn_status fail(rtn_status code, const char* fmt, ...) {
 
 }  // namespace
 
+rtn_status rtn::failf(rtn_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
 rtn_status rtn::hip_fail(hipError_t e, const char* what) {
   return fail(RTN_EHIP, "%s: %s", what, hipGetErrorString(e));
 }

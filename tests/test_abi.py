@@ -203,3 +203,49 @@ def test_profile_read_without_records(lib):
     assert lib.rtn_profile_enable(0) == RTN_OK
     assert lib.rtn_profile_read(None, 0, ctypes.byref(n)) == RTN_OK
     assert n.value == 0
+
+
+def test_di_param_count_matches_table_ii(lib):
+    """Parameter counts of the double-integrator networks of Table II (2 inputs, 2 outputs)."""
+    n = ctypes.c_int64()
+    printed = {(2, 16): 354, (2, 128): 17e3, (5, 16): 1.2e3, (5, 128): 67e3, (12, 32): 12e3, (50, 512): 13e6}
+    for (L, H), want in printed.items():
+        assert lib.rtn_di_param_count(L, H, ctypes.byref(n)) == RTN_OK
+        if L == 2 and H == 16:
+            assert n.value == want
+        else:
+            assert abs(n.value - want) / want < 0.05, (L, H, n.value, want)
+    for L, H in ((0, 16), (65, 16), (2, 0), (2, 8193)):
+        assert lib.rtn_di_param_count(L, H, ctypes.byref(n)) == RTN_EINVAL
+
+
+def test_di_validation(lib):
+    z = ctypes.c_void_p(16)
+    assert lib.rtn_di_model_create(2, 16, 0, None, ctypes.byref(ctypes.c_void_p())) == RTN_EINVAL
+    assert lib.rtn_di_model_create(2, 16, 5, z, ctypes.byref(ctypes.c_void_p())) == RTN_EINVAL
+    assert lib.rtn_di_model_destroy(None) == RTN_OK
+    lin = lambda dt, n, p=z: lib.rtn_di_linearize(None, ctypes.c_float(dt), n, p, p, p, p, p, None, None, None)
+    assert lin(0.0, 4) == RTN_EINVAL
+    assert lin(0.05, -1) == RTN_EINVAL
+    assert lin(0.05, 4, None) == RTN_EINVAL
+    assert lin(0.05, 0, None) == RTN_OK
+    Q = np.eye(2)
+    R = np.array([0.1])
+    Rbad = np.array([0.0])
+    qp, rp, rb = (a.ctypes.data_as(ctypes.c_void_p) for a in (Q, R, Rbad))
+
+    def rti(n_inst, off, n, r=rp, q=qp, p=z):
+        o = None
+        if off is not None:
+            arr = np.asarray(off, dtype=np.int32)
+            rti._keep = arr
+            o = arr.ctypes.data_as(ctypes.c_void_p)
+        return lib.rtn_di_rti(None, ctypes.c_float(0.05), n_inst, o, n, q, r, q, p, p, p, p, None, p, p, p,
+                              None, None, None, None)
+    assert rti(1, None, 0) == RTN_OK
+    assert rti(1, None, 4, r=rb) == RTN_EINVAL
+    assert rti(1, None, 4, q=None) == RTN_EINVAL
+    assert rti(2, [0, 2, 2], 2) == RTN_EINVAL
+    assert rti(1, None, 4, p=None) == RTN_EINVAL
+    assert rti(2, [0, 3, 516], 516) == RTN_ENOTSUP                     # 513 nodes in one instance
+    assert b"at most 512" in lib.rtn_last_error()

@@ -1,0 +1,199 @@
+"""GPU parity of the double-integrator runtime workload (Sec. V) against the FP64
+oracle: the network value and Jacobian (forward-mode tangents on the GPU,
+reverse accumulation in the oracle), the RK4 linearisation, and one real-time
+iteration (Riccati recursion and rollout in fp64).
+
+Bounds: x_{k+1}, A_k, B_k within 1e-5 (fp32) of the oracle, as per-node
+relative Frobenius errors; f_D-bar and J_D within 1e-5, and 1e-4 for widths
+above 1024 (fp32 sums of up to 8192 products); the LQ step within 1e-9 of the
+oracle's Riccati and rollout run on the GPU's own A_k, B_k and x_{k+1}.
+"""
+import numpy as np
+import pytest
+
+from oracle.double_integrator import linearize as di_oracle, rti_step
+from oracle.mlp import MLP
+from oracle.riccati import riccati, lq_rollout
+from workload import xavier_params
+
+pytestmark = pytest.mark.gpu
+DT = 0.05
+Q = np.eye(2)
+R = np.array([[0.1]])
+QN = np.diag([2.0, 1.0])
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-30)
+
+
+def di_net(L, H, seed, zero_out=False):
+    Ws, bs = xavier_params(L, H, seed=seed, d_in=2, d_out=2)
+    rng = np.random.default_rng(seed + 7)
+    bs = [rng.uniform(-0.3, 0.3, size=b.shape).astype(np.float32) for b in bs]
+    if zero_out:  # the paper's runtime runs: the output layer returns 0
+        Ws[-1] = np.zeros_like(Ws[-1])
+        bs[-1] = np.zeros_like(bs[-1])
+    return Ws, bs
+
+
+def di_nodes(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.stack([rng.uniform(-2, 2, n), rng.normal(0, 1, n)], axis=1).astype(np.float32)
+    u = rng.uniform(-1, 1, n).astype(np.float32)
+    return x, u
+
+
+def gpu_lin(torch, x, u, Ws, bs):
+    import paper_2203_07747_amd as rtn
+    print(f"[gpu] di_linearize n={x.shape[0]} L={len(Ws) - 1 if Ws else '-'} H={Ws[0].shape[0] if Ws else '-'}",
+          flush=True)
+    m = rtn.DiModel(Ws, bs) if Ws is not None else None
+    out = rtn.di_linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), m, DT)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if m is not None:
+        m.close()
+    return res
+
+
+@pytest.mark.parametrize("L,H,n", [(1, 1, 3), (2, 2, 10), (2, 3, 11), (3, 7, 23), (2, 16, 10), (5, 16, 31),
+                                   (2, 64, 1), (2, 100, 10), (3, 128, 25), (2, 512, 10), (12, 32, 10),
+                                   (2, 1024, 13)])
+def test_di_linearize_matches_oracle(torch, L, H, n):
+    Ws, bs = di_net(L, H, seed=L * 100 + H)
+    x, u = di_nodes(n, seed=H + n)
+    res = gpu_lin(torch, x, u, Ws, bs)
+    ref = di_oracle(x, u[:, None], MLP(Ws, bs), DT)
+    errs = {k: float(rel(res[k].reshape(n, -1), r.reshape(n, -1)).max())
+            for k, r in zip(("x_next", "A", "B", "f_D", "J_D"), ref)}
+    print("  max rel err:", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for k in ("x_next", "A", "B", "f_D", "J_D"):
+        assert errs[k] <= 1e-5, (k, errs[k])
+
+
+@pytest.mark.parametrize("H", [4096, 8192])
+def test_di_wide_two_layer_network(torch, H):
+    """The widest networks of the paper's two-layer sweep (Sec. V), 10 nodes."""
+    Ws, bs = di_net(2, H, seed=H)
+    x, u = di_nodes(10, seed=3)
+    res = gpu_lin(torch, x, u, Ws, bs)
+    ref = di_oracle(x, u[:, None], MLP(Ws, bs), DT)
+    errs = {k: float(rel(res[k].reshape(10, -1), r.reshape(10, -1)).max())
+            for k, r in zip(("x_next", "A", "B", "f_D", "J_D"), ref)}
+    print("  max rel err:", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for k in ("x_next", "A", "B"):
+        assert errs[k] <= 1e-5, (k, errs[k])
+    assert errs["f_D"] <= 1e-4 and errs["J_D"] <= 1e-4
+
+
+def test_di_zero_output_network_and_nominal(torch):
+    """With the output layer set to zero (the paper's runtime runs) the step is the
+    exact double-integrator kinematics, as with no network at all."""
+    x, u = di_nodes(10, seed=4)
+    Ws, bs = di_net(2, 64, seed=5, zero_out=True)
+    for res in (gpu_lin(torch, x, u, Ws, bs), gpu_lin(torch, x, u, None, None)):
+        assert np.all(res["f_D"] == 0) and np.all(res["J_D"] == 0)
+        ref = di_oracle(x, u[:, None], None, DT)
+        for k, r in zip(("x_next", "A", "B"), ref):
+            np.testing.assert_allclose(res[k].reshape(10, -1), r.reshape(10, -1), rtol=1e-6, atol=1e-7)
+
+
+def run_rti(torch, Ws, bs, offsets, seed, model=None):
+    import paper_2203_07747_amd as rtn
+    n, n_inst = int(offsets[-1]), len(offsets) - 1
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0, 1, (n, 2)).astype(np.float32)
+    u = rng.normal(0, 1, n).astype(np.float32)
+    xN = rng.normal(0, 1, (n_inst, 2)).astype(np.float32)
+    x0 = rng.normal(0, 1, (n_inst, 2)).astype(np.float32)
+    xr = rng.normal(0, 1, (n_inst, 2)).astype(np.float32)
+    print(f"[gpu] di_rti n={n} n_inst={n_inst} H={Ws[0].shape[0] if Ws else '-'}", flush=True)
+    own = model is None and Ws is not None
+    if own:
+        model = rtn.DiModel(Ws, bs)
+    t = lambda a: torch.from_numpy(a).cuda()
+    out = rtn.di_rti(t(x), t(u), t(xN), t(x0), model, Q, R, QN, DT, offsets=offsets, x_ref=t(xr),
+                     want_linearisation=True)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if own:
+        model.close()
+    return res, (x, u, xN, x0, xr)
+
+
+def check_rti(res, data, offsets, net):
+    x, u, xN, x0, xr = data
+    n = x.shape[0]
+    # the linearisation against the oracle
+    ref = di_oracle(x, u[:, None], net, DT)
+    for k, r in zip(("x_next", "A", "B"), ref):
+        assert rel(res[k].reshape(n, -1), r.reshape(n, -1)).max() <= 1e-5, k
+    # the LQ step against the oracle's Riccati and rollout on the GPU's own linearisation
+    A = res["A"].astype(np.float64)
+    B = res["B"].astype(np.float64)[:, :, None]
+    xn = res["x_next"].astype(np.float64)
+    for i in range(len(offsets) - 1):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        succ = np.concatenate([x[a + 1:b], xN[i:i + 1]], axis=0).astype(np.float64)
+        c = xn[a:b] - succ
+        e = x[a:b].astype(np.float64) - xr[i]
+        K, kff, _ = riccati(A[a:b], B[a:b], Q, R, QN, c=c, q=e @ Q.T, r=u[a:b, None].astype(np.float64) @ R.T,
+                            qN=QN @ (xN[i].astype(np.float64) - xr[i]))
+        du, dx = lq_rollout(A[a:b], B[a:b], K, kff, x0[i].astype(np.float64) - x[a], c)
+        scale = max(np.abs(du).max(), 1.0)
+        np.testing.assert_allclose(res["du"][a:b], du[:, 0], rtol=1e-9, atol=1e-9 * scale)
+        np.testing.assert_allclose(res["dx"][a:b], dx[:-1], rtol=1e-9, atol=1e-9 * scale)
+        np.testing.assert_allclose(res["dxN"][i], dx[-1], rtol=1e-9, atol=1e-9 * scale)
+    # and end to end against the fp64 real-time iteration
+    du, dx, dxN, _ = rti_step(offsets, x, u[:, None], xN, x0, net, DT, Q, R, QN, xref=xr)
+    err = np.abs(res["du"] - du[:, 0]).max() / max(np.abs(du).max(), 1e-30)
+    print(f"  end-to-end du rel err vs fp64 iteration {err:.1e}", flush=True)
+    assert err < 1e-3
+
+
+@pytest.mark.parametrize("L,H,offsets", [(2, 16, [0, 10]), (2, 512, [0, 10, 17, 18]), (3, 100, [0, 5, 45]),
+                                         (0, 0, [0, 10, 20])])
+def test_di_rti_matches_oracle(torch, L, H, offsets):
+    offsets = np.array(offsets)
+    Ws, bs = di_net(L, H, seed=H + 1) if L else (None, None)
+    res, data = run_rti(torch, Ws, bs, offsets, seed=L + H)
+    check_rti(res, data, offsets, MLP(Ws, bs) if Ws else None)
+
+
+def test_di_rti_graph_replay_sees_new_data(torch):
+    """Repeated calls replay one captured graph; new values in the same buffers are used."""
+    import paper_2203_07747_amd as rtn
+    Ws, bs = di_net(2, 256, seed=9)
+    m = rtn.DiModel(Ws, bs)
+    net = MLP(Ws, bs)
+    offsets = np.array([0, 10])
+    rng = np.random.default_rng(1)
+    bufs = None
+    out = None
+    for it in range(3):
+        x = rng.normal(0, 1, (10, 2)).astype(np.float32)
+        u = rng.normal(0, 1, 10).astype(np.float32)
+        xN = rng.normal(0, 1, (1, 2)).astype(np.float32)
+        x0 = rng.normal(0, 1, (1, 2)).astype(np.float32)
+        if bufs is None:
+            bufs = [torch.from_numpy(a).cuda() for a in (x, u, xN, x0)]
+        else:
+            for b, a in zip(bufs, (x, u, xN, x0)):
+                b.copy_(torch.from_numpy(a))
+        print(f"[gpu] di_rti replay {it}", flush=True)
+        out = rtn.di_rti(*bufs, m, Q, R, QN, DT, offsets=offsets, want_linearisation=True, out=out)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        check_rti(res, (x, u, xN, x0, np.zeros((1, 2), np.float32)), offsets, net)
+    m.close()

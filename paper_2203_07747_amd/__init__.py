@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, INPUT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "DiModel", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "DiModel", "DiRtiCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -570,3 +570,40 @@ def di_rti(x, u, xN, x0, model: Optional[DiModel], Q, R, QN, dt: float = 0.05, o
                             _dev(A, f32, (n, 2, 2), "A"), _dev(B, f32, (n, 2), "B"), _dev(xn, f32, (n, 2), "x_next"),
                             _stream(stream)), "rtn_di_rti")
     return out
+
+
+class DiRtiCall:
+    """rtn_di_rti with its arguments checked and marshalled once: each call only
+    enqueues the iteration (the library replays its captured graph), for control
+    loops that refill the same input tensors every tick."""
+
+    def __init__(self, x, u, xN, x0, model: Optional[DiModel], Q, R, QN, dt: float = 0.05, offsets=None,
+                 x_ref=None, want_linearisation: bool = False, stream=None):
+        self.out = di_rti(x, u, xN, x0, model, Q, R, QN, dt, offsets, x_ref, want_linearisation, stream=stream)
+        torch = _torch()
+        n = x.shape[0]
+        self._keep = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (Q, R, QN)]
+        if offsets is None:
+            n_inst, off = 1, None
+        else:
+            off_arr = np.ascontiguousarray(offsets, dtype=np.int32)
+            self._keep.append(off_arr)
+            n_inst, off = off_arr.size - 1, off_arr.ctypes.data_as(ctypes.c_void_p)
+        o = self.out
+        f32, f64 = torch.float32, torch.float64
+        self._fn = load().rtn_di_rti
+        self._args = (model.handle if model is not None else None, ctypes.c_float(dt), n_inst, off, n,
+                      *(a.ctypes.data_as(ctypes.c_void_p) for a in self._keep[:3]),
+                      _dev(x, f32, (n, 2), "x"), _dev(u, f32, (n,), "u"), _dev(xN, f32, (n_inst, 2), "xN"),
+                      _dev(x0, f32, (n_inst, 2), "x0"), _dev(x_ref, f32, (n_inst, 2), "x_ref"),
+                      _dev(o["du"], f64, (n,), "du"), _dev(o["dx"], f64, (n, 2), "dx"),
+                      _dev(o["dxN"], f64, (n_inst, 2), "dxN"),
+                      _dev(o.get("A"), f32, (n, 2, 2), "A"), _dev(o.get("B"), f32, (n, 2), "B"),
+                      _dev(o.get("x_next"), f32, (n, 2), "x_next"), _stream(stream))
+        self._tensors = (x, u, xN, x0, x_ref, model)  # keep the buffers alive
+
+    def __call__(self) -> Dict[str, object]:
+        code = self._fn(*self._args)
+        if code != 0:
+            check(code, "rtn_di_rti")
+        return self.out

@@ -14,11 +14,23 @@ constexpr int kDiMaxWidth = 8192;
 constexpr int kDiMaxHorizon = 512;  // nodes per instance in one real-time iteration
 
 // Activations of a node batch: three rows per node, [value h_l; dh_l/dp; dh_l/dv],
-// row-major [3n][width].
+// for widths that are a multiple of 8 in MFMA operand order (node tiles of 10
+// nodes padded to 32 rows), else row-major [3n][width]; di_z_floats is the size.
+inline bool di_packed(int H) { return H % 8 == 0; }
+size_t di_z_floats(int n, int H);
+// Hidden weights W [H][H] (row-major) -> the operand order of the packed path,
+// (H+31)/32 * 32 * H floats, zero padded (host).
+void di_pack_weight(const float* W, int H, float* out);
+inline size_t di_packed_weight_floats(int H) { return (size_t)(H + 31) / 32 * 32 * H; }
 hipError_t launch_di_first_layer(int n, int H, const float* W, const float* b, int act, const float* x, float* Z,
                                  hipStream_t st);
-hipError_t launch_di_hidden_layer(int n, int K, int N, const float* Zin, const float* W, const float* b, int act,
-                                  float* Zout, hipStream_t st);
+// Wide layers split K into di_slices(n, H) slices (one workgroup each) to fill
+// the device; a second kernel adds their partial tiles (di_partial_floats of
+// scratch) in slice order.
+int di_slices(int n, int H);
+size_t di_partial_floats(int n, int H);
+hipError_t launch_di_hidden_layer(int n, int H, const float* Zin, const float* W, const float* b, int act,
+                                  float* Zout, float* partial, hipStream_t st);
 hipError_t launch_di_output_layer(int n, int K, const float* W, const float* b, const float* Z, float* y, float* J,
                                   hipStream_t st);
 // Per node RK4 step of the nominal model plus the affine residual (y, J nullable = 0).

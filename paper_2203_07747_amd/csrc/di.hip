@@ -36,6 +36,23 @@ __device__ inline float di_act(float a, int act, float* dact) {
   return a;
 }
 
+// Position of activation row w (0 value, 1 d/dp, 2 d/dv) of node i, feature k, in
+// a [3n][H] array: row-major, or (packed) in MFMA operand order, node tiles of 10
+// nodes (30 rows padded to 32), then K-groups of 8, then the 64 lanes' float4s:
+//   ((tile * H/8 + k/8) * 64 + lane) * 4 + k%4,  lane = row-in-tile + 32 ((k%8)/4),
+// so that each wave's operand load is one contiguous 1 KB run.
+template <bool PK>
+__device__ inline size_t zpos(int i, int w, int k, int H) {
+  if constexpr (PK) {
+    const int tile = i / kNodesPerTile, r = 3 * (i - tile * kNodesPerTile) + w;
+    const int lane = r + 32 * ((k >> 2) & 1);
+    return (((size_t)tile * (H >> 3) + (k >> 3)) * 64 + lane) * 4 + (k & 3);
+  } else {
+    return ((size_t)3 * i + w) * H + k;
+  }
+}
+
+template <bool PK>
 __global__ void __launch_bounds__(256) di_first_layer(int n, int H, const float* __restrict__ W,
                                                       const float* __restrict__ b, int act,
                                                       const float* __restrict__ x, float* __restrict__ Z) {
@@ -45,41 +62,45 @@ __global__ void __launch_bounds__(256) di_first_layer(int n, int H, const float*
   const float w0 = W[2 * c], w1 = W[2 * c + 1];
   float d;
   const float h = di_act(fmaf(w0, x[2 * i], fmaf(w1, x[2 * i + 1], b[c])), act, &d);
-  float* z = Z + (size_t)3 * i * H + c;
-  z[0] = h;
-  z[H] = d * w0;
-  z[2 * (size_t)H] = d * w1;
+  Z[zpos<PK>(i, 0, c, H)] = h;
+  Z[zpos<PK>(i, 1, c, H)] = d * w0;
+  Z[zpos<PK>(i, 2, c, H)] = d * w1;
 }
 
-// Zout = epilogue(Zin W^T) for W [N][K] row-major; one workgroup per 32 output
-// columns and 10 nodes, its waves splitting K.  MFMA 32x32x2 fp32: lane l
-// supplies row (or column) l % 32 and, for the 4 products of one group of 8
-// K-values, k = 8 j + 4 (l / 32) + t; both operands are read as float4 along K
-// (VEC, K % 8 == 0) or element by element (small odd widths).
-template <bool VEC>
+// Zout = epilogue(Zin W^T) for W [N][K]; one workgroup per 32 output columns,
+// 10 nodes and one of KS slices of K, its waves splitting the slice.  MFMA
+// 32x32x2 fp32: lane l supplies row (or column) l % 32 and, for the 4 products
+// of one group of 8 K-values, k = 8 j + 4 (l / 32) + t.  PK (K % 8 == 0): Zin,
+// Zout and W are in operand order (zpos; W packed the same way by column tiles,
+// zero padded), so every operand load is a contiguous float4 per lane with no
+// bounds check; otherwise row-major with element loads (small odd widths).
+// With KS > 1 every workgroup stores its slice's partial tile and
+// di_hidden_fixup adds the slices in order and applies the epilogue.
+template <bool PK>
 __global__ void __launch_bounds__(kMaxWaves * kWave)
 di_hidden_layer(int n, int K, int N, const float* __restrict__ Zin, const float* __restrict__ W,
-                const float* __restrict__ b, int act, float* __restrict__ Zout) {
+                const float* __restrict__ b, int act, float* __restrict__ Zout, float* __restrict__ partial) {
   __shared__ float part[kMaxWaves][kTileRows * 33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int c0 = blockIdx.x * 32, node0 = blockIdx.y * kNodesPerTile;
+  const int KS = gridDim.z, slice = blockIdx.z;
   const int rows = 3 * min(kNodesPerTile, n - node0);
   const int r = lane & 31, h = lane >> 5;
-  const bool rv = r < rows, cv = c0 + r < N;
-  const float* za = Zin + ((size_t)node0 * 3 + (rv ? r : 0)) * K;
-  const float* wb = W + (size_t)(cv ? c0 + r : 0) * K;
   const int groups = (K + 7) / 8;
+  const int per = (groups + KS - 1) / KS;
+  const int g0 = slice * per, g1 = min(groups, g0 + per);
   f32x16 acc = {};
-  if constexpr (VEC) {
+  if constexpr (PK) {
+    const float4* ap = reinterpret_cast<const float4*>(Zin) + (size_t)blockIdx.y * groups * 64 + lane;
+    const float4* bp = reinterpret_cast<const float4*>(W) + (size_t)blockIdx.x * groups * 64 + lane;
     constexpr int U = 4;  // groups in flight per wave
-    int j = wave;
-    for (; j + (U - 1) * nw < groups; j += U * nw) {
+    int j = g0 + wave;
+    for (; j + (U - 1) * nw < g1; j += U * nw) {
       float4 av[U], bv[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int k = 8 * (j + q * nw) + 4 * h;
-        av[q] = rv ? *reinterpret_cast<const float4*>(za + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-        bv[q] = cv ? *reinterpret_cast<const float4*>(wb + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+        av[q] = ap[(size_t)(j + q * nw) * 64];
+        bv[q] = bp[(size_t)(j + q * nw) * 64];
       }
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -89,17 +110,18 @@ di_hidden_layer(int n, int K, int N, const float* __restrict__ Zin, const float*
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].w, bv[q].w, acc, 0, 0, 0);
       }
     }
-    for (; j < groups; j += nw) {
-      const int k = 8 * j + 4 * h;
-      const float4 a4 = rv ? *reinterpret_cast<const float4*>(za + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float4 b4 = cv ? *reinterpret_cast<const float4*>(wb + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (; j < g1; j += nw) {
+      const float4 a4 = ap[(size_t)j * 64], b4 = bp[(size_t)j * 64];
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
     }
   } else {
-    for (int j = wave; j < groups; j += nw) {
+    const bool rv = r < rows, cv = c0 + r < N;
+    const float* za = Zin + ((size_t)node0 * 3 + (rv ? r : 0)) * K;
+    const float* wb = W + (size_t)(cv ? c0 + r : 0) * K;
+    for (int j = g0 + wave; j < g1; j += nw) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int k = 8 * j + 4 * h + t;
@@ -116,6 +138,15 @@ di_hidden_layer(int n, int K, int N, const float* __restrict__ Zin, const float*
     if (row < kTileRows) part[wave][row * 33 + r] = acc[i];
   }
   __syncthreads();
+  if (KS > 1) {  // this slice's tile, summed over the waves in wave order
+    float* pt = partial + (((size_t)slice * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kTileRows * 32;
+    for (int e = threadIdx.x; e < kTileRows * 32; e += blockDim.x) {
+      float v = 0.f;
+      for (int w = 0; w < nw; ++w) v += part[w][(e >> 5) * 33 + (e & 31)];
+      pt[e] = v;
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < kNodesPerTile * 32; e += blockDim.x) {
     const int q = e >> 5, cc = e & 31, node = node0 + q, col = c0 + cc;
     if (3 * q >= rows || col >= N) continue;
@@ -127,27 +158,48 @@ di_hidden_layer(int n, int K, int N, const float* __restrict__ Zin, const float*
     }
     float d;
     const float hv = di_act(s0 + b[col], act, &d);
-    float* zo = Zout + (size_t)3 * node * N + col;
-    zo[0] = hv;
-    zo[N] = d * s1;
-    zo[2 * (size_t)N] = d * s2;
+    Zout[zpos<PK>(node, 0, col, N)] = hv;
+    Zout[zpos<PK>(node, 1, col, N)] = d * s1;
+    Zout[zpos<PK>(node, 2, col, N)] = d * s2;
   }
 }
 
+// Sum of the KS partial tiles (in slice order) and the layer epilogue.
+template <bool PK>
+__global__ void __launch_bounds__(320) di_hidden_fixup(int n, int N, int KS, const float* __restrict__ partial,
+                                                       const float* __restrict__ b, int act, float* __restrict__ Zout) {
+  const int q = threadIdx.x >> 5, cc = threadIdx.x & 31;
+  const int node = blockIdx.y * kNodesPerTile + q, col = blockIdx.x * 32 + cc;
+  if (node >= n || col >= N) return;
+  const size_t stride = (size_t)gridDim.y * gridDim.x * kTileRows * 32;
+  const float* pp = partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kTileRows * 32 + cc;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int sl = 0; sl < KS; ++sl) {
+    s0 += pp[sl * stride + (3 * q) * 32];
+    s1 += pp[sl * stride + (3 * q + 1) * 32];
+    s2 += pp[sl * stride + (3 * q + 2) * 32];
+  }
+  float d;
+  const float hv = di_act(s0 + b[col], act, &d);
+  Zout[zpos<PK>(node, 0, col, N)] = hv;
+  Zout[zpos<PK>(node, 1, col, N)] = d * s1;
+  Zout[zpos<PK>(node, 2, col, N)] = d * s2;
+}
+
 // y[i][j] = W[j] . h + b[j], J[i][j][m] = W[j] . T_m: one workgroup per (node, output).
+template <bool PK>
 __global__ void __launch_bounds__(256) di_output_layer(int n, int K, const float* __restrict__ W,
                                                        const float* __restrict__ b, const float* __restrict__ Z,
                                                        float* __restrict__ y, float* __restrict__ J) {
   __shared__ float red[3][4];
   const int i = blockIdx.x >> 1, j = blockIdx.x & 1, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const float* w = W + (size_t)j * K;
-  const float* z = Z + (size_t)3 * i * K;
   float s0 = 0.f, s1 = 0.f, s2 = 0.f;
   for (int k = t; k < K; k += 256) {
     const float wk = w[k];
-    s0 = fmaf(wk, z[k], s0);
-    s1 = fmaf(wk, z[K + k], s1);
-    s2 = fmaf(wk, z[2 * (size_t)K + k], s2);
+    s0 = fmaf(wk, Z[zpos<PK>(i, 0, k, K)], s0);
+    s1 = fmaf(wk, Z[zpos<PK>(i, 1, k, K)], s1);
+    s2 = fmaf(wk, Z[zpos<PK>(i, 2, k, K)], s2);
   }
   for (int off = 32; off > 0; off >>= 1) {
     s0 += __shfl_xor(s0, off);
@@ -164,6 +216,46 @@ __global__ void __launch_bounds__(256) di_output_layer(int n, int K, const float
     y[2 * i + j] = red[0][0] + red[0][1] + red[0][2] + red[0][3] + b[j];
     J[(2 * i + j) * 2 + 0] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     J[(2 * i + j) * 2 + 1] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  }
+  (void)n;
+}
+
+// Packed path: one workgroup per node, each thread a set of K-groups of 8;
+// the node's three rows of a group are six float4s of the operand order and
+// the two output rows two float4s each.
+__global__ void __launch_bounds__(256) di_output_packed(int n, int K, const float* __restrict__ W,
+                                                        const float* __restrict__ b, const float* __restrict__ Z,
+                                                        float* __restrict__ y, float* __restrict__ J) {
+  __shared__ float red[6][4];
+  const int i = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int G = K >> 3, tile = i / kNodesPerTile, r0 = 3 * (i - tile * kNodesPerTile);
+  const float4* z4 = reinterpret_cast<const float4*>(Z) + (size_t)tile * G * 64;
+  const float4* w0 = reinterpret_cast<const float4*>(W);
+  const float4* w1 = reinterpret_cast<const float4*>(W + K);
+  float s[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  for (int j = t; j < G; j += 256) {
+    const float4 a0 = w0[2 * j], a1 = w0[2 * j + 1], c0 = w1[2 * j], c1 = w1[2 * j + 1];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const float4 lo = z4[(size_t)j * 64 + r0 + w], hi = z4[(size_t)j * 64 + r0 + w + 32];
+      s[0][w] += a0.x * lo.x + a0.y * lo.y + a0.z * lo.z + a0.w * lo.w + a1.x * hi.x + a1.y * hi.y + a1.z * hi.z +
+                 a1.w * hi.w;
+      s[1][w] += c0.x * lo.x + c0.y * lo.y + c0.z * lo.z + c0.w * lo.w + c1.x * hi.x + c1.y * hi.y + c1.z * hi.z +
+                 c1.w * hi.w;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    float v = s[q / 3][q % 3];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[q][wave] = v;
+  }
+  __syncthreads();
+  if (t < 6) {
+    const float v = red[t][0] + red[t][1] + red[t][2] + red[t][3];
+    const int jo = t / 3, w = t % 3;
+    if (w == 0) y[2 * i + jo] = v + b[jo];
+    else J[(2 * i + jo) * 2 + (w - 1)] = v;
   }
   (void)n;
 }
@@ -334,30 +426,77 @@ hipError_t launch_di_first_layer(int n, int H, const float* W, const float* b, i
                                  hipStream_t st) {
   const long total = (long)n * H;
   if (total <= 0) return hipSuccess;
-  di_first_layer<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(n, H, W, b, act, x, Z);
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (di_packed(H))
+    di_first_layer<true><<<blocks, 256, 0, st>>>(n, H, W, b, act, x, Z);
+  else
+    di_first_layer<false><<<blocks, 256, 0, st>>>(n, H, W, b, act, x, Z);
   return hipGetLastError();
 }
 
-hipError_t launch_di_hidden_layer(int n, int K, int N, const float* Zin, const float* W, const float* b, int act,
-                                  float* Zout, hipStream_t st) {
-  if (n <= 0 || N <= 0) return hipSuccess;
-  const int groups = (K + 7) / 8;
-  int nw = groups / 8;  // about eight groups of eight K-values per wave
+int di_slices(int n, int H) {
+  // wide layers: K split so that about two workgroups per compute unit stream
+  // the weights (the partial tiles are small next to the weights they replace)
+  (void)n;
+  if (H < 2048 || H >= 8192) return 1;  // at 8192 one workgroup per CU already streams near the bound
+  int ks = 512 / ((H + 31) / 32);
+  if (ks > 8) ks = 8;
+  return ks < 1 ? 1 : ks;
+}
+
+size_t di_partial_floats(int n, int H) {
+  const size_t tiles = (size_t)(n + kNodesPerTile - 1) / kNodesPerTile, ct = (H + 31) / 32;
+  const int ks = di_slices(n, H);
+  return ks > 1 ? (size_t)ks * tiles * ct * kTileRows * 32 : 0;
+}
+
+hipError_t launch_di_hidden_layer(int n, int H, const float* Zin, const float* W, const float* b, int act,
+                                  float* Zout, float* partial, hipStream_t st) {
+  if (n <= 0 || H <= 0) return hipSuccess;
+  const int groups = (H + 7) / 8, ks = di_slices(n, H);
+  int nw = (groups / ks) / 8;  // about eight groups of eight K-values per wave
   if (nw > kMaxWaves) nw = kMaxWaves;
   if (nw < 1) nw = 1;
-  dim3 grid((N + 31) / 32, (n + kNodesPerTile - 1) / kNodesPerTile);
-  if (K % 8 == 0)
-    di_hidden_layer<true><<<grid, nw * kWave, 0, st>>>(n, K, N, Zin, W, b, act, Zout);
+  dim3 grid((H + 31) / 32, (n + kNodesPerTile - 1) / kNodesPerTile, ks);
+  const bool pk = di_packed(H);
+  if (pk)
+    di_hidden_layer<true><<<grid, nw * kWave, 0, st>>>(n, H, H, Zin, W, b, act, Zout, partial);
   else
-    di_hidden_layer<false><<<grid, nw * kWave, 0, st>>>(n, K, N, Zin, W, b, act, Zout);
+    di_hidden_layer<false><<<grid, nw * kWave, 0, st>>>(n, H, H, Zin, W, b, act, Zout, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  dim3 g2(grid.x, grid.y);
+  if (pk)
+    di_hidden_fixup<true><<<g2, kNodesPerTile * 32, 0, st>>>(n, H, ks, partial, b, act, Zout);
+  else
+    di_hidden_fixup<false><<<g2, kNodesPerTile * 32, 0, st>>>(n, H, ks, partial, b, act, Zout);
   return hipGetLastError();
 }
 
 hipError_t launch_di_output_layer(int n, int K, const float* W, const float* b, const float* Z, float* y, float* J,
                                   hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  di_output_layer<<<2 * n, 256, 0, st>>>(n, K, W, b, Z, y, J);
+  if (di_packed(K))
+    di_output_packed<<<n, 256, 0, st>>>(n, K, W, b, Z, y, J);
+  else
+    di_output_layer<false><<<2 * n, 256, 0, st>>>(n, K, W, b, Z, y, J);
   return hipGetLastError();
+}
+
+size_t di_z_floats(int n, int H) {
+  const size_t tiles = (size_t)(n + kNodesPerTile - 1) / kNodesPerTile;
+  return di_packed(H) ? tiles * 32 * H : (size_t)3 * n * H;
+}
+
+void di_pack_weight(const float* W, int H, float* out) {
+  const int G = H / 8, CT = (H + 31) / 32;
+  for (int ct = 0; ct < CT; ++ct)
+    for (int j = 0; j < G; ++j)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 4; ++t) {
+          const int row = 32 * ct + (lane & 31), k = 8 * j + 4 * (lane >> 5) + t;
+          out[(((size_t)ct * G + j) * 64 + lane) * 4 + t] = row < H ? W[(size_t)row * H + k] : 0.f;
+        }
 }
 
 hipError_t launch_di_linearize(int n, float dt, const float* x, const float* u, const float* y, const float* J,

@@ -28,6 +28,7 @@ struct rtn_di_model {
   // workspace: activations [2][3n][H], f_D [n][2], J_D [n][2][2]; instance offsets
   float* Z = nullptr;
   float* yJ = nullptr;
+  float* partial = nullptr;  // split-K partial tiles of the hidden layers
   int64_t cap = 0;
   int* d_off = nullptr;
   std::vector<int32_t> off_host;
@@ -43,7 +44,7 @@ struct rtn_di_model {
   ~rtn_di_model() {
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (void* p : {(void*)params, (void*)Z, (void*)yJ, (void*)d_off})
+    for (void* p : {(void*)params, (void*)Z, (void*)yJ, (void*)partial, (void*)d_off})
       if (p) (void)hipFree(p);
   }
   void drop_graphs() {
@@ -71,14 +72,15 @@ rtn_status ensure_ws(rtn_di_model* m, int64_t n, hipStream_t st) {
   if (n <= m->cap) return RTN_OK;
   m->drop_graphs();
   DI_TRY(hipStreamSynchronize(st));
-  if (m->Z) (void)hipFree(m->Z);
-  if (m->yJ) (void)hipFree(m->yJ);
-  m->Z = nullptr;
-  m->yJ = nullptr;
+  for (void** p : {(void**)&m->Z, (void**)&m->yJ, (void**)&m->partial}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
   m->cap = 0;
   const int H = m->H;
-  hipError_t e = hipMalloc((void**)&m->Z, (size_t)2 * 3 * n * H * 4);
+  hipError_t e = hipMalloc((void**)&m->Z, 2 * di_z_floats((int)n, H) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&m->yJ, (size_t)n * 6 * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->partial, di_partial_floats((int)n, H) * 4 + 16);
   if (e != hipSuccess) return failf(RTN_ENOMEM, "workspace for %lld nodes: %s", (long long)n, hipGetErrorString(e));
   m->cap = n;
   return RTN_OK;
@@ -86,7 +88,7 @@ rtn_status ensure_ws(rtn_di_model* m, int64_t n, hipStream_t st) {
 
 // Network value and Jacobian of n nodes into y [n][2], J [n][2][2].
 hipError_t enqueue_network(const rtn_di_model* m, int n, const float* x, float* y, float* J, hipStream_t st) {
-  const size_t zs = (size_t)3 * n * m->H;
+  const size_t zs = di_z_floats(n, m->H);
   float* Za = m->Z;
   float* Zb = m->Z + zs;
   hipError_t e;
@@ -97,8 +99,8 @@ hipError_t enqueue_network(const rtn_di_model* m, int n, const float* x, float* 
   }
   for (int l = 1; l < m->L; ++l) {
     ProfScope ps("di_hidden_layer", st);
-    if ((e = launch_di_hidden_layer(n, m->H, m->H, Za, m->params + m->w_off[l], m->params + m->b_off[l], m->act, Zb,
-                                    st)))
+    if ((e = launch_di_hidden_layer(n, m->H, Za, m->params + m->w_off[l], m->params + m->b_off[l], m->act, Zb,
+                                    m->partial, st)))
       return e;
     std::swap(Za, Zb);
   }
@@ -135,15 +137,19 @@ rtn_status rtn_di_model_create(int32_t n_hidden, int32_t width, int32_t activati
   m->H = width;
   m->act = activation == RTN_ACT_SILU ? 0 : 1;
   m->n_params = count;
-  // device layout: the user's tensors in order, each starting on a 256-byte boundary
+  // device layout: the user's tensors in order, each starting on a 256-byte
+  // boundary; hidden-to-hidden weights in the operand order of the packed path
+  // when the width allows it
+  const bool pk = di_packed(m->H);
   std::vector<int64_t> user_off;
   int64_t off = 0, uoff = 0;
   auto align = [](int64_t v) { return (v + 63) / 64 * 64; };
   for (int l = 0; l <= m->L; ++l) {
     const int64_t nw = (int64_t)m->fan_out(l) * m->fan_in(l), nb = m->fan_out(l);
+    const bool hid = l > 0 && l < m->L;
     m->w_off.push_back(off);
     user_off.push_back(uoff);
-    off = align(off + nw);
+    off = align(off + (hid && pk ? (int64_t)di_packed_weight_floats(m->H) : nw));
     uoff += nw;
     m->b_off.push_back(off);
     user_off.push_back(uoff);
@@ -155,9 +161,15 @@ rtn_status rtn_di_model_create(int32_t n_hidden, int32_t width, int32_t activati
     delete m;
     return failf(RTN_ENOMEM, "hipMalloc(%lld bytes): %s", (long long)off * 4, hipGetErrorString(e));
   }
+  std::vector<float> packed(pk && m->L > 1 ? di_packed_weight_floats(m->H) : 0);
   for (int l = 0; l <= m->L && e == hipSuccess; ++l) {
     const int64_t nw = (int64_t)m->fan_out(l) * m->fan_in(l), nb = m->fan_out(l);
-    e = hipMemcpy(m->params + m->w_off[l], params_host + user_off[2 * l], nw * 4, hipMemcpyHostToDevice);
+    if (pk && l > 0 && l < m->L) {
+      di_pack_weight(params_host + user_off[2 * l], m->H, packed.data());
+      e = hipMemcpy(m->params + m->w_off[l], packed.data(), packed.size() * 4, hipMemcpyHostToDevice);
+    } else {
+      e = hipMemcpy(m->params + m->w_off[l], params_host + user_off[2 * l], nw * 4, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess)
       e = hipMemcpy(m->params + m->b_off[l], params_host + user_off[2 * l + 1], nb * 4, hipMemcpyHostToDevice);
   }

@@ -69,7 +69,7 @@ def gpu_lin(torch, x, u, Ws, bs):
 
 @pytest.mark.parametrize("L,H,n", [(1, 1, 3), (2, 2, 10), (2, 3, 11), (3, 7, 23), (2, 16, 10), (5, 16, 31),
                                    (2, 64, 1), (2, 100, 10), (3, 128, 25), (2, 512, 10), (12, 32, 10),
-                                   (2, 1024, 13)])
+                                   (2, 1024, 13), (2, 1024, 25), (2, 1000, 12), (3, 2048, 21)])
 def test_di_linearize_matches_oracle(torch, L, H, n):
     Ws, bs = di_net(L, H, seed=L * 100 + H)
     x, u = di_nodes(n, seed=H + n)

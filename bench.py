@@ -98,8 +98,14 @@ def parse():
     return p.parse_args()
 
 
-def time_steps(torch, fn, steps, warmup, stream):
+def time_steps(torch, fn, steps, warmup, stream, warm_s: float = 0.0):
+    """Mean ms per call over `steps` back-to-back calls (HIP events on `stream`) and the
+    host wall time per call, after `warmup` calls and at least `warm_s` seconds of them
+    (short calls after a pause otherwise run before the clocks have come up)."""
     for _ in range(warmup):
+        fn()
+    t_end = time.perf_counter() + warm_s
+    while time.perf_counter() < t_end:
         fn()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -190,7 +196,7 @@ def extras(torch, rtn, lin_out, off, stream):
     with torch.cuda.graph(gph, stream=cap):
         t1.add_(1.0)
     torch.cuda.synchronize()
-    ms, _ = time_steps(torch, gph.replay, 200, 20, stream)
+    ms, _ = time_steps(torch, gph.replay, 200, 20, stream, warm_s=0.05)
     res["graph_launch_floor_us"] = ms * 1e3
     for key in ("c1", "c2"):
         cfg, o, x, u, Ws, bs = config_workload(key)
@@ -198,7 +204,7 @@ def extras(torch, rtn, lin_out, off, stream):
         xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
         out = {}
         f = lambda: rtn.linearize(xt, ut, m, "fp32", cfg.dt, offsets=o, out=out, stream=stream)
-        ms, wall = time_steps(torch, f, 200, 20, stream)
+        ms, wall = time_steps(torch, f, 200, 20, stream, warm_s=0.05)
         rtn.profile_enable(True)
         for _ in range(20):
             f()
@@ -285,10 +291,7 @@ def di_runtime(torch, rtn, stream):
             m = rtn.DiModel(Ws, bs)
         call = rtn.DiRtiCall(x, u, xN, x0, m, Q, R, QN, dt, stream=stream)
         # warm up for 50 ms of back-to-back iterations (clocks settle after the model build)
-        t_end = time.perf_counter() + 0.05
-        while time.perf_counter() < t_end:
-            call()
-        ms, wall = time_steps(torch, call, 400, 20, stream)
+        ms, wall = time_steps(torch, call, 400, 20, stream, warm_s=0.05)
         out = {}
         f = lambda: rtn.di_rti(x, u, xN, x0, m, Q, R, QN, dt, out=out, stream=stream)
         ms_py, _ = time_steps(torch, f, 200, 20, stream)

@@ -57,6 +57,9 @@ template <int P, int H, bool REV> struct ChainShapeDefault {
 //   V = 3: reverse, bf16/fp8 width 512: one wave per SIMD, 128 rows, all 256
 //          accumulator registers in use -- a quarter less weight traffic from
 //          L2 per matrix product than 96 rows.
+//   V = 4: bf16/fp8 width 512: 128 rows over 8 waves (two per SIMD, each 2
+//          M-tiles x 4 row tiles), one workgroup per CU: half the weight
+//          traffic of two 64-row workgroups, and a 4-step weight ring.
 // OCC is the number of waves per SIMD the register budget is sized for.
 template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
   using D = ChainShapeDefault<P, H, REV>;
@@ -67,7 +70,8 @@ template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
   static constexpr bool FITS64 = 64 * H * ESZ + (REV ? 12 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
                                  (H / 32 / 4) * 2 * 16 <= 128;
   static constexpr int R2 = FITS64 ? 64 : 32;
-  static constexpr int NW = V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : 4;
+  static constexpr int NW =
+      V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : V == 4 ? 8 : 4;
   static constexpr int R =
       V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : V == 2 ? R2 : 128;
   static constexpr int OCC = V == 2 ? 2 : (NW <= 4 ? 1 : 2);
@@ -75,7 +79,7 @@ template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
       V == 0 || (V == 1 && H >= 512 && R >= 32) ||
       (V == 2 && H >= 512 && R * H * ESZ + (REV ? 7 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
        (H / 32 / 4) * (R / 32) * 16 <= 128) ||
-      (V == 3 && REV && H == 512 && P != P_FP32);
+      (V == 3 && REV && H == 512 && P != P_FP32) || (V == 4 && H == 512 && P != P_FP32);
 };
 
 // OCC: waves per SIMD the kernel is built for (1: the whole register file and,
@@ -751,17 +755,18 @@ template <int P, int H, int V> hipError_t chain_geom_v(int rev, int occupancy, C
 }
 
 #define RTN_CHAIN_SWITCH(FN, ...)                              \
-  switch (H * 4 + V) {                                         \
-    case 64 * 4: return FN<P, 64, 0>(__VA_ARGS__);             \
-    case 128 * 4: return FN<P, 128, 0>(__VA_ARGS__);           \
-    case 256 * 4: return FN<P, 256, 0>(__VA_ARGS__);           \
-    case 512 * 4: return FN<P, 512, 0>(__VA_ARGS__);           \
-    case 512 * 4 + 1: return FN<P, 512, 1>(__VA_ARGS__);       \
-    case 512 * 4 + 2: return FN<P, 512, 2>(__VA_ARGS__);       \
-    case 512 * 4 + 3: return FN<P, 512, 3>(__VA_ARGS__);       \
-    case 1024 * 4: return FN<P, 1024, 0>(__VA_ARGS__);         \
-    case 1024 * 4 + 1: return FN<P, 1024, 1>(__VA_ARGS__);     \
-    case 1024 * 4 + 2: return FN<P, 1024, 2>(__VA_ARGS__);     \
+  switch (H * 8 + V) {                                         \
+    case 64 * 8: return FN<P, 64, 0>(__VA_ARGS__);             \
+    case 128 * 8: return FN<P, 128, 0>(__VA_ARGS__);           \
+    case 256 * 8: return FN<P, 256, 0>(__VA_ARGS__);           \
+    case 512 * 8: return FN<P, 512, 0>(__VA_ARGS__);           \
+    case 512 * 8 + 1: return FN<P, 512, 1>(__VA_ARGS__);       \
+    case 512 * 8 + 2: return FN<P, 512, 2>(__VA_ARGS__);       \
+    case 512 * 8 + 3: return FN<P, 512, 3>(__VA_ARGS__);       \
+    case 512 * 8 + 4: return FN<P, 512, 4>(__VA_ARGS__);       \
+    case 1024 * 8: return FN<P, 1024, 0>(__VA_ARGS__);         \
+    case 1024 * 8 + 1: return FN<P, 1024, 1>(__VA_ARGS__);     \
+    case 1024 * 8 + 2: return FN<P, 1024, 2>(__VA_ARGS__);     \
     default: return hipErrorInvalidValue;                      \
   }
 

@@ -34,13 +34,13 @@ hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int tra
 hipError_t launch_amax(const float* a, long n, float* out, hipStream_t st);
 hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st);
 // Launch configuration of a layer-chain kernel: tile variant (0 = default
-// shape, 1..3 = alternative shapes, widths 512 and 1024 only) and workgroup
+// shape, 1..4 = alternative shapes, widths 512 and 1024 only) and workgroup
 // count (0 = two per compute unit; never more than there are row blocks).
 struct ChainCfg {
   int variant = 0;
   int grid = 0;
 };
-constexpr int kChainVariants = 4;
+constexpr int kChainVariants = 5;
 // Tile shape of a (precision, width, direction, variant): whether it exists,
 // waves per workgroup, rows per workgroup, and (when `occupancy` is set; this
 // asks the device) workgroups resident per compute unit, else 0.

@@ -290,8 +290,9 @@ def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
     try:
         for choice in [(0, 0, 0, 0, 0), (0, 1, 0, 1, 0), (0, 1, 1, 1, 1), (0, 0, 3, 1, 7), (0, 1, 5, 0, 2),
                        (0, 0, 10000, 0, 10000), (0, 2, 0, 2, 0), (0, 2, 3, 2, 5), (0, 2, 10000, 2, 1),
-                       (0, 0, 0, 3, 0), (0, 2, 0, 3, 3)]:
-            if choice[3] == 3 and (prec == "fp32" or H != 512):
+                       (0, 0, 0, 3, 0), (0, 2, 0, 3, 3), (0, 2, 0, 4, 0), (0, 0, 0, 4, 3), (0, 4, 0, 4, 0),
+                       (0, 4, 5, 0, 0)]:
+            if (choice[3] in (3, 4) or choice[1] == 4) and (prec == "fp32" or H != 512):
                 continue
             print(f"[gpu] tile choice {choice} prec={prec} H={H} L={L} n={n}", flush=True)
             rtn.tune_set(prec, H, L, n, choice)

@@ -566,46 +566,45 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     {
       const float inv = P == P_FP8 ? 1.f / net.gscale[L - 1] : 1.f;
       float lmax = 0.f;
-      // Every thread handles ITEMS (row tile, K-step, lane) items; they are taken
-      // in groups of GI whose reads are all issued before any is used, so the
-      // read latency is paid once per group.  Rows past the end read node0 / row 0
-      // (valid addresses) and are zeroed by a mask, so no read is predicated.
-      constexpr int TOTAL = C::RT * C::KS_H * kWave;
-      static_assert(TOTAL % NT == 0, "operand items must split evenly over the threads");
-      constexpr int ITEMS = TOTAL / NT;
-      constexpr int GI = C::E >= 32 ? 1 : (ITEMS % 4 == 0 ? 4 : (ITEMS % 2 == 0 ? 2 : 1));
+      // Work unit = (K-step, lane group, output j, quarter of the rows): the unit
+      // loads the E weights W_{L+1}[j][slots] once and applies them to its rows
+      // with row % 6 == j (every 24th row of the block), so each weight value is
+      // read from L2 once per unit rather than once per row -- the L2 round trips
+      // of these reads otherwise dominate this phase.  Rows past the end are
+      // written as zeros.
+      constexpr int NU = C::KS_H * 2 * kDout * 4;
+      const int jr = row0 % 6;
 #pragma unroll 1
-      for (int i0 = 0; i0 < ITEMS; i0 += GI) {
-        float spv[GI][C::E], wv[GI][C::E], msk[GI];
-        int rts[GI], ss[GI];
+      for (int u = tid; u < NU; u += NT) {
+        const int qr = u & 3, j = (u >> 2) % kDout, gg = (u / (4 * kDout)) & 1, sk = u / (8 * kDout);
+        float wv[C::E];
 #pragma unroll
-        for (int gi = 0; gi < GI; ++gi) {
-          const int it = tid + (i0 + gi) * NT;
-          const int l = it % kWave, sk = (it / kWave) % C::KS_H, rt = it / (kWave * C::KS_H);
-          const int row = row0 + rt * 32 + (l & 31), gg = l >> 5;
+        for (int run = 0; run < C::E / RL; ++run) {
+          const int q0 = sk * C::E + run * RL;
+          const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
+          load_run<RL>(wo + j * wo_stride + pos, wv + run * RL);
+        }
+        // block rows i with (row0 + i) % 6 == j, this quarter: i = i0 + 6 qr + 24 m
+        const int i0 = (j - jr + 6) % 6 + 6 * qr;
+#pragma unroll 2
+        for (int i = i0; i < R; i += 24) {
+          const int row = row0 + i;
           const bool live = row < nrows;
-          const int node = live ? row / 6 : node0, j6 = live ? row - 6 * node : 0;
-          msk[gi] = live ? 1.f : 0.f;
-          rts[gi] = rt;
-          ss[gi] = sk;
+          const int node = live ? row / 6 : node0;
+          float v[C::E];
 #pragma unroll
           for (int run = 0; run < C::E / RL; ++run) {
             const int q0 = sk * C::E + run * RL;
-            const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
-            load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, spv[gi] + run * RL);
-            load_run<RL>(wo + j6 * wo_stride + pos, wv[gi] + run * RL);
+            const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);
+            load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, v + run * RL);
           }
-        }
 #pragma unroll
-        for (int gi = 0; gi < GI; ++gi) {
-          float v[C::E];
-#pragma unroll
-          for (int t = 0; t < C::E; ++t) v[t] = wv[gi][t] * spv[gi][t] * msk[gi];
+          for (int t = 0; t < C::E; ++t) v[t] = live ? wv[t] * v[t] : 0.f;
           if (amax) {
 #pragma unroll
-            for (int j = 0; j < C::E; ++j) lmax = fmaxf(lmax, fabsf(v[j]));
+            for (int t = 0; t < C::E; ++t) lmax = fmaxf(lmax, fabsf(v[t]));
           }
-          C::put_slots(lds, rts[gi], ss[gi], tid % kWave, C::KS_H, v, inv);
+          C::put_slots(lds, i >> 5, sk, gg * 32 + (i & 31), C::KS_H, v, inv);
         }
       }
       if (amax) atomic_amax(&amax[L - 1], lmax);

@@ -45,4 +45,14 @@ hipError_t launch_di_rti(int n_inst, const int* offsets, float dt, const DiCost&
                          const float* xN, const float* x0, const float* xref, const float* y, const float* J,
                          double* du, double* dx, double* dxN, float* A, float* B, float* xn, hipStream_t st);
 
+// The whole iteration in one workgroup per instance for small networks
+// (di_fused_fits: width <= 64, <= 64 nodes per instance).  `fused` holds
+// W_1, b_1, then W_l^T (k-major), b_l for the hidden layers, then W_out, b_out;
+// woff [2L + 2] (device) their offsets.
+bool di_fused_fits(int H, int max_horizon);
+hipError_t launch_di_fused(int n_inst, const int* offsets, int L, int H, int act, const float* fused,
+                           const long* woff, float dt, const DiCost& cost, const float* x, const float* u,
+                           const float* xN, const float* x0, const float* xref, double* du, double* dx, double* dxN,
+                           float* A, float* B, float* xn, hipStream_t st);
+
 }  // namespace rtn

@@ -332,47 +332,30 @@ __global__ void __launch_bounds__(256) di_linearize_kernel(int n, float dt, cons
 // Per node LQ data in LDS (fp64): A 4 | B 2 | c 2 | q 2 | r 1 | K 2 | kff 1.
 constexpr int kLqStride = 14;
 
-// One instance per workgroup: the RK4 linearisation of its nodes (parallel),
-// then the Riccati recursion and the rollout (sequential in k, one lane):
+// Stage node k of an instance (global node `node`) for the LQ solve: its
+// linearisation (A, B, gap c = x_next - x_{k+1}) and the cost gradients.
+__device__ inline void di_stage_node(double* s, int k, int N, int node, int inst, const DiCost& cost, double xr0,
+                                     double xr1, const float* x, const float* u, const float* xN, const float* xo,
+                                     const float* Ao, const float* Bo) {
+  const float* succ = k + 1 < N ? x + 2 * (node + 1) : xN + 2 * inst;
+  for (int i = 0; i < 4; ++i) s[i] = Ao[i];
+  s[4] = Bo[0];
+  s[5] = Bo[1];
+  s[6] = (double)xo[0] - (double)succ[0];
+  s[7] = (double)xo[1] - (double)succ[1];
+  const double e0 = (double)x[2 * node] - xr0, e1 = (double)x[2 * node + 1] - xr1;
+  s[8] = cost.Q[0] * e0 + cost.Q[1] * e1;
+  s[9] = cost.Q[2] * e0 + cost.Q[3] * e1;
+  s[10] = cost.R * (double)u[node];
+}
+
+// The Riccati recursion and the rollout of one instance on one lane:
 //   Quu = R + B^T P B,  Qux = B^T P A,  g = P c + p,  qx = q + A^T g,  qu = r + B^T g
 //   K = -Qux / Quu,  kff = -qu / Quu,  P <- sym(Q + A^T P A + Qux^T K),  p <- qx + Qux^T kff
 //   du_k = K dx_k + kff,  dx_{k+1} = A dx_k + B du_k + c_k,  dx_0 = x0 - x_0.
-__global__ void __launch_bounds__(64) di_rti_kernel(const int* __restrict__ offsets, float dt, DiCost cost,
-                                                    const float* __restrict__ x, const float* __restrict__ u,
-                                                    const float* __restrict__ xN, const float* __restrict__ x0,
-                                                    const float* __restrict__ xref, const float* __restrict__ y,
-                                                    const float* __restrict__ J, double* __restrict__ du,
-                                                    double* __restrict__ dx, double* __restrict__ dxN,
-                                                    float* __restrict__ Aout, float* __restrict__ Bout,
-                                                    float* __restrict__ xnout) {
-  __shared__ double sm[kDiMaxHorizon * kLqStride];
-  const int inst = blockIdx.x, t = threadIdx.x;
-  const int k0 = offsets[inst], N = offsets[inst + 1] - k0;
-  const double xr0 = xref ? xref[2 * inst] : 0.0, xr1 = xref ? xref[2 * inst + 1] : 0.0;
-  for (int k = t; k < N; k += 64) {
-    const int node = k0 + k;
-    float xo[2], Ao[4], Bo[2];
-    di_node(node, dt, x, u, y, J, xo, Ao, Bo);
-    if (xnout)
-      for (int i = 0; i < 2; ++i) xnout[2 * node + i] = xo[i];
-    if (Aout)
-      for (int i = 0; i < 4; ++i) Aout[4 * node + i] = Ao[i];
-    if (Bout)
-      for (int i = 0; i < 2; ++i) Bout[2 * node + i] = Bo[i];
-    const float* succ = k + 1 < N ? x + 2 * (node + 1) : xN + 2 * inst;
-    double* s = sm + k * kLqStride;
-    for (int i = 0; i < 4; ++i) s[i] = Ao[i];
-    s[4] = Bo[0];
-    s[5] = Bo[1];
-    s[6] = (double)xo[0] - (double)succ[0];
-    s[7] = (double)xo[1] - (double)succ[1];
-    const double e0 = (double)x[2 * node] - xr0, e1 = (double)x[2 * node + 1] - xr1;
-    s[8] = cost.Q[0] * e0 + cost.Q[1] * e1;
-    s[9] = cost.Q[2] * e0 + cost.Q[3] * e1;
-    s[10] = cost.R * (double)u[node];
-  }
-  __syncthreads();
-  if (t != 0) return;
+__device__ inline void di_lq_solve(double* sm, int N, int k0, int inst, const DiCost& cost, double xr0, double xr1,
+                                   const float* x, const float* xN, const float* x0, double* du, double* dx,
+                                   double* dxN) {
   const double* Q = cost.Q;
   double P00 = cost.QN[0], P01 = cost.QN[1], P10 = cost.QN[2], P11 = cost.QN[3];
   const double eN0 = (double)xN[2 * inst] - xr0, eN1 = (double)xN[2 * inst + 1] - xr1;
@@ -418,6 +401,164 @@ __global__ void __launch_bounds__(64) di_rti_kernel(const int* __restrict__ offs
   }
   dxN[2 * inst] = d0;
   dxN[2 * inst + 1] = d1;
+}
+
+__device__ inline void di_store_lin(int node, const float* xo, const float* Ao, const float* Bo, float* xnout,
+                                    float* Aout, float* Bout) {
+  if (xnout)
+    for (int i = 0; i < 2; ++i) xnout[2 * node + i] = xo[i];
+  if (Aout)
+    for (int i = 0; i < 4; ++i) Aout[4 * node + i] = Ao[i];
+  if (Bout)
+    for (int i = 0; i < 2; ++i) Bout[2 * node + i] = Bo[i];
+}
+
+// One instance per workgroup: the RK4 linearisation of its nodes (parallel, with
+// the network's value and Jacobian from the layer kernels), then the LQ solve.
+__global__ void __launch_bounds__(64) di_rti_kernel(const int* __restrict__ offsets, float dt, DiCost cost,
+                                                    const float* __restrict__ x, const float* __restrict__ u,
+                                                    const float* __restrict__ xN, const float* __restrict__ x0,
+                                                    const float* __restrict__ xref, const float* __restrict__ y,
+                                                    const float* __restrict__ J, double* __restrict__ du,
+                                                    double* __restrict__ dx, double* __restrict__ dxN,
+                                                    float* __restrict__ Aout, float* __restrict__ Bout,
+                                                    float* __restrict__ xnout) {
+  __shared__ double sm[kDiMaxHorizon * kLqStride];
+  const int inst = blockIdx.x, t = threadIdx.x;
+  const int k0 = offsets[inst], N = offsets[inst + 1] - k0;
+  const double xr0 = xref ? xref[2 * inst] : 0.0, xr1 = xref ? xref[2 * inst + 1] : 0.0;
+  for (int k = t; k < N; k += 64) {
+    const int node = k0 + k;
+    float xo[2], Ao[4], Bo[2];
+    di_node(node, dt, x, u, y, J, xo, Ao, Bo);
+    di_store_lin(node, xo, Ao, Bo, xnout, Aout, Bout);
+    di_stage_node(sm + k * kLqStride, k, N, node, inst, cost, xr0, xr1, x, u, xN, xo, Ao, Bo);
+  }
+  __syncthreads();
+  if (t == 0) di_lq_solve(sm, N, k0, inst, cost, xr0, xr1, x, xN, x0, du, dx, dxN);
+}
+
+// Small networks (width <= 64, instances of <= 64 nodes): the whole iteration in
+// one workgroup per instance -- every layer, value and tangent rows, with the
+// activations in LDS and the hidden weights read transposed (Wt[k][c] = W[c][k],
+// so a wave's weight loads are contiguous), then RK4 and the LQ solve -- one
+// launch instead of L + 2.  Nodes are taken 10 at a time (30 activation rows).
+constexpr int kFusedMaxWidth = 64;  // wider layers run faster as separate kernels
+constexpr int kFusedMaxHorizon = 64;
+constexpr int kFusedThreads = 256;
+
+template <int MAXS>
+__global__ void __launch_bounds__(kFusedThreads)
+di_fused_small(const int* __restrict__ offsets, int L, int H, int act, const float* __restrict__ params,
+               const long* __restrict__ woff, float dt, DiCost cost, const float* __restrict__ x,
+               const float* __restrict__ u, const float* __restrict__ xN, const float* __restrict__ x0,
+               const float* __restrict__ xref, double* __restrict__ du, double* __restrict__ dx,
+               double* __restrict__ dxN, float* __restrict__ Aout, float* __restrict__ Bout,
+               float* __restrict__ xnout) {
+  // activation rows [30][ZS]: the odd stride puts the 32 rows an MFMA operand
+  // read touches on 32 different banks
+  constexpr int ZS = kFusedMaxWidth + 1;
+  __shared__ float za[kTileRows * ZS], zb[kTileRows * ZS], sraw[kTileRows * ZS];
+  __shared__ float yj[kNodesPerTile * 6];
+  __shared__ double sm[kFusedMaxHorizon * kLqStride];
+  const int inst = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6, r = lane & 31, hh = lane >> 5;
+  const int k0 = offsets[inst], N = offsets[inst + 1] - k0;
+  const double xr0 = xref ? xref[2 * inst] : 0.0, xr1 = xref ? xref[2 * inst + 1] : 0.0;
+  // this wave's 32-column tile of every hidden layer (at most one per wave)
+  const int c = wave * 32 + r;
+  const bool cv = c < H, rv = r < kTileRows, has_tile = wave * 32 < H;
+  const int steps = (H + 1) / 2;  // <= MAXS
+  // the lane's weights of hidden layer l (k = 2 s + l / 32), requested one layer ahead
+  float bv[MAXS];
+  auto fetch = [&](int l) {
+    const float* Wt = params + woff[2 * l];
+#pragma unroll
+    for (int st = 0; st < MAXS; ++st) {
+      const int k = 2 * st + hh;
+      bv[st] = (cv && k < H) ? Wt[k * H + c] : 0.f;
+    }
+  };
+  // woff: W_1, b_1, W_2^T, b_2, ..., W_out, b_out offsets into params
+  for (int n0 = 0; n0 < N; n0 += kNodesPerTile) {
+    const int nn = min(kNodesPerTile, N - n0);
+    if (L > 1) fetch(1);
+    {  // layer 1: h_1 and its tangents, per (node, column)
+      const float* W1 = params + woff[0];
+      const float* b1 = params + woff[1];
+      for (int e = t; e < nn * H; e += kFusedThreads) {
+        const int q = e / H, cc = e - q * H, node = k0 + n0 + q;
+        const float w0 = W1[2 * cc], w1 = W1[2 * cc + 1];
+        float d;
+        const float hv = di_act(fmaf(w0, x[2 * node], fmaf(w1, x[2 * node + 1], b1[cc])), act, &d);
+        za[(3 * q) * ZS + cc] = hv;
+        za[(3 * q + 1) * ZS + cc] = d * w0;
+        za[(3 * q + 2) * ZS + cc] = d * w1;
+      }
+    }
+    __syncthreads();
+    float* zi = za;
+    float* zo = zb;
+    for (int l = 1; l < L; ++l) {
+      // S = Z W_l^T on MFMA 32x32x2 fp32: lane l supplies activation row l % 32 and
+      // weight column l % 32 at k = 2 s + l / 32
+      if (has_tile) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int st = 0; st < MAXS; ++st) {
+          if (st < steps) {
+            const int k = 2 * st + hh;
+            const float a = (rv && k < H) ? zi[r * ZS + k] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv[st], acc, 0, 0, 0);
+          }
+        }
+        if (l + 1 < L) fetch(l + 1);  // the next layer's weights load during this epilogue
+        // accumulator register i: row (i/4)*8 + (l/32)*4 + i%4, column l%32
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int row = (i >> 2) * 8 + hh * 4 + (i & 3);
+          if (row < kTileRows && cv) sraw[row * ZS + c] = acc[i];
+        }
+      }
+      __syncthreads();
+      const float* bl = params + woff[2 * l + 1];
+      for (int e = t; e < nn * H; e += kFusedThreads) {  // bias, act, act' gating of the tangent rows
+        const int q = e / H, cc = e - q * H;
+        float d;
+        const float hv = di_act(sraw[(3 * q) * ZS + cc] + bl[cc], act, &d);
+        zo[(3 * q) * ZS + cc] = hv;
+        zo[(3 * q + 1) * ZS + cc] = d * sraw[(3 * q + 1) * ZS + cc];
+        zo[(3 * q + 2) * ZS + cc] = d * sraw[(3 * q + 2) * ZS + cc];
+      }
+      __syncthreads();
+      float* tmp = zi;
+      zi = zo;
+      zo = tmp;
+    }
+    {  // output layer: y = W_out h + b, J = W_out T (60 dot products of length H)
+      const float* Wo = params + woff[2 * L];
+      const float* bo = params + woff[2 * L + 1];
+      if (t < nn * 6) {
+        const int q = t / 6, rr = t - 6 * q, j = rr / 3, w = rr - 3 * j;
+        float sacc = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < H; ++k) sacc = fmaf(Wo[j * H + k], zi[(3 * q + w) * ZS + k], sacc);
+        // yj[q][0..1] = y, yj[q][2..5] = J row-major
+        if (w == 0) yj[6 * q + j] = sacc + bo[j];
+        else yj[6 * q + 2 + 2 * j + (w - 1)] = sacc;
+      }
+    }
+    __syncthreads();
+    if (t < nn) {  // RK4 of each node with its own f_D-bar, J_D
+      const int k = n0 + t, node = k0 + k;
+      const float xk[2] = {x[2 * node], x[2 * node + 1]};
+      float xo[2], Ao[4], Bo[2];
+      di_rk4(xk, u[node], yj + 6 * t, yj + 6 * t + 2, dt, xo, Ao, Bo);
+      di_store_lin(node, xo, Ao, Bo, xnout, Aout, Bout);
+      di_stage_node(sm + k * kLqStride, k, N, node, inst, cost, xr0, xr1, x, u, xN, xo, Ao, Bo);
+    }
+    __syncthreads();
+  }
+  if (t == 0) di_lq_solve(sm, N, k0, inst, cost, xr0, xr1, x, xN, x0, du, dx, dxN);
 }
 
 }  // namespace
@@ -503,6 +644,23 @@ hipError_t launch_di_linearize(int n, float dt, const float* x, const float* u, 
                                float* xn, float* A, float* B, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   di_linearize_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, dt, x, u, y, J, xn, A, B);
+  return hipGetLastError();
+}
+
+bool di_fused_fits(int H, int max_horizon) { return H <= kFusedMaxWidth && max_horizon <= kFusedMaxHorizon; }
+
+hipError_t launch_di_fused(int n_inst, const int* offsets, int L, int H, int act, const float* fused,
+                           const long* woff, float dt, const DiCost& cost, const float* x, const float* u,
+                           const float* xN, const float* x0, const float* xref, double* du, double* dx, double* dxN,
+                           float* A, float* B, float* xn, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  if (H > kFusedMaxWidth || H < 1) return hipErrorInvalidValue;
+  if (H <= 32)
+    di_fused_small<16><<<n_inst, kFusedThreads, 0, st>>>(offsets, L, H, act, fused, woff, dt, cost, x, u, xN, x0,
+                                                         xref, du, dx, dxN, A, B, xn);
+  else
+    di_fused_small<32><<<n_inst, kFusedThreads, 0, st>>>(offsets, L, H, act, fused, woff, dt, cost, x, u, xN, x0,
+                                                         xref, du, dx, dxN, A, B, xn);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // argument validation and dispatch of the kernels in di.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -29,6 +30,8 @@ struct rtn_di_model {
   float* Z = nullptr;
   float* yJ = nullptr;
   float* partial = nullptr;  // split-K partial tiles of the hidden layers
+  float* fused = nullptr;    // small widths: the single-workgroup path's weights (hidden ones transposed)
+  long* fused_off = nullptr;
   int64_t cap = 0;
   int* d_off = nullptr;
   std::vector<int32_t> off_host;
@@ -44,7 +47,7 @@ struct rtn_di_model {
   ~rtn_di_model() {
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (void* p : {(void*)params, (void*)Z, (void*)yJ, (void*)partial, (void*)d_off})
+    for (void* p : {(void*)params, (void*)Z, (void*)yJ, (void*)partial, (void*)d_off, (void*)fused, (void*)fused_off})
       if (p) (void)hipFree(p);
   }
   void drop_graphs() {
@@ -173,6 +176,28 @@ rtn_status rtn_di_model_create(int32_t n_hidden, int32_t width, int32_t activati
     if (e == hipSuccess)
       e = hipMemcpy(m->params + m->b_off[l], params_host + user_off[2 * l + 1], nb * 4, hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess && di_fused_fits(m->H, 1)) {
+    // the single-workgroup path for small widths: W_1, b_1, W_l^T, b_l, ..., W_out, b_out
+    std::vector<float> f;
+    std::vector<long> fo;
+    for (int l = 0; l <= m->L; ++l) {
+      const int fo_ = m->fan_out(l), fi = m->fan_in(l);
+      const float* W = params_host + user_off[2 * l];
+      fo.push_back((long)f.size());
+      if (l > 0 && l < m->L) {
+        for (int k = 0; k < fi; ++k)
+          for (int c = 0; c < fo_; ++c) f.push_back(W[(size_t)c * fi + k]);
+      } else {
+        f.insert(f.end(), W, W + (size_t)fo_ * fi);
+      }
+      fo.push_back((long)f.size());
+      f.insert(f.end(), params_host + user_off[2 * l + 1], params_host + user_off[2 * l + 1] + fo_);
+    }
+    e = hipMalloc((void**)&m->fused, f.size() * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&m->fused_off, fo.size() * sizeof(long));
+    if (e == hipSuccess) e = hipMemcpy(m->fused, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->fused_off, fo.data(), fo.size() * sizeof(long), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     delete m;
     return hip_fail(e, "copying parameters");
@@ -232,10 +257,13 @@ rtn_status rtn_di_rti(const rtn_di_model* model, float dt, int32_t n_inst, const
   if (!du || !dx || !dxN) return failf(RTN_EINVAL, "du, dx and dxN must be device pointers");
   std::vector<int32_t> off(offsets_host ? offsets_host : nullptr, offsets_host ? offsets_host + n_inst + 1 : nullptr);
   if (!offsets_host) off = {0, n_nodes};
-  for (int i = 0; i < n_inst; ++i)
+  int max_h = 0;
+  for (int i = 0; i < n_inst; ++i) {
     if (off[i + 1] - off[i] > kDiMaxHorizon)
       return failf(RTN_ENOTSUP, "instance %d has %d nodes; at most %d per instance", i, off[i + 1] - off[i],
                    kDiMaxHorizon);
+    max_h = std::max(max_h, off[i + 1] - off[i]);
+  }
   hipStream_t st = (hipStream_t)stream;
   rtn_di_model* m = const_cast<rtn_di_model*>(model);
   // instance offsets and the nominal-only case use a model-independent holder
@@ -257,9 +285,15 @@ rtn_status rtn_di_rti(const rtn_di_model* model, float dt, int32_t n_inst, const
     DI_TRY(hipMemcpy(h->d_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
     h->off_host = off;
   }
+  const bool fused = m && m->fused && di_fused_fits(m->H, max_h);
   float* y = m ? m->yJ : nullptr;
   float* J = m ? m->yJ + (size_t)2 * n_nodes : nullptr;
   auto enqueue = [&](hipStream_t q) -> hipError_t {
+    if (fused) {
+      ProfScope ps("di_fused_small", q);
+      return launch_di_fused(n_inst, h->d_off, m->L, m->H, m->act, m->fused, m->fused_off, dt, cost, x, u, xN, x0,
+                             x_ref, du, dx, dxN, A, B, x_next, q);
+    }
     if (m) {
       hipError_t e = enqueue_network(m, n_nodes, x, y, J, q);
       if (e != hipSuccess) return e;

@@ -171,6 +171,17 @@ def test_di_rti_matches_oracle(torch, L, H, offsets):
     check_rti(res, data, offsets, MLP(Ws, bs) if Ws else None)
 
 
+@pytest.mark.parametrize("L,H,offsets", [(5, 64, [0, 23, 87]), (2, 7, [0, 64]), (12, 32, [0, 10, 11, 30]),
+                                         (1, 48, [0, 10]), (3, 33, [0, 13]), (2, 16, [0, 65]), (5, 128, [0, 23])])
+def test_di_rti_small_networks(torch, L, H, offsets):
+    """Widths up to 64 with instances of up to 64 nodes take the single-workgroup
+    path (several 10-node tiles here); 65 nodes or width 128 use the layer kernels."""
+    offsets = np.array(offsets)
+    Ws, bs = di_net(L, H, seed=3 * H + L)
+    res, data = run_rti(torch, Ws, bs, offsets, seed=H)
+    check_rti(res, data, offsets, MLP(Ws, bs))
+
+
 def test_di_rti_graph_replay_sees_new_data(torch):
     """Repeated calls replay one captured graph; new values in the same buffers are used."""
     import paper_2203_07747_amd as rtn

@@ -95,6 +95,8 @@ def parse():
                    help="skip the latency, Riccati and training side measurements")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a 64 MiB device copy (counter calibration for the traffic figures)")
+    p.add_argument("--di", metavar="LxH", default=None,
+                   help="only time the double-integrator real-time iteration of one network (e.g. 2x8192)")
     return p.parse_args()
 
 
@@ -269,7 +271,7 @@ PAPER_RTX3000_HZ_TABLE_II = {(2, 16): 781, (2, 128): 770, (5, 16): 586, (5, 128)
                              (12, 512): 363, (20, 512): 232, (50, 512): 117}
 
 
-def di_runtime(torch, rtn, stream):
+def di_runtime(torch, rtn, stream, only=None):
     """The runtime workload of Sec. V: one real-time iteration (network value and
     Jacobian, RK4 linearisation, Riccati recursion, rollout) of the double integrator
     with N = 10 nodes per call, for the two-layer width sweep and the networks of
@@ -300,6 +302,11 @@ def di_runtime(torch, rtn, stream):
         return {"us_per_iteration": ms * 1e3, "hz": 1e3 / ms, "host_us_per_call": wall * 1e3,
                 "us_per_iteration_unprepared_python_call": ms_py * 1e3}
 
+    if only is not None:
+        L, H = only
+        r = tick_time(L, H)
+        r["weight_bytes"] = 4.0 * (3 * H + (L - 1) * (H * H + H) + 2 * H + 2)
+        return {"nodes": N, "network": f"{L}x{H}", **r}
     res = {"nodes": N, "loop": "back-to-back rtn_di_rti calls (prepared arguments, captured graph), "
                                "timed with events on the stream",
            "nominal_only": tick_time(0, 0), "two_layer": {}, "table_ii": {}}
@@ -319,6 +326,12 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.di:
+        import torch
+        import paper_2203_07747_amd as rtn
+        L, H = (int(v) for v in args.di.lower().split("x"))
+        print(json.dumps(di_runtime(torch, rtn, torch.cuda.current_stream(), only=(L, H))), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -187,7 +187,6 @@ __global__ void __launch_bounds__(320) di_hidden_fixup(int n, int N, int KS, con
 }
 
 // y[i][j] = W[j] . h + b[j], J[i][j][m] = W[j] . T_m: one workgroup per (node, output).
-template <bool PK>
 __global__ void __launch_bounds__(256) di_output_layer(int n, int K, const float* __restrict__ W,
                                                        const float* __restrict__ b, const float* __restrict__ Z,
                                                        float* __restrict__ y, float* __restrict__ J) {
@@ -197,9 +196,9 @@ __global__ void __launch_bounds__(256) di_output_layer(int n, int K, const float
   float s0 = 0.f, s1 = 0.f, s2 = 0.f;
   for (int k = t; k < K; k += 256) {
     const float wk = w[k];
-    s0 = fmaf(wk, Z[zpos<PK>(i, 0, k, K)], s0);
-    s1 = fmaf(wk, Z[zpos<PK>(i, 1, k, K)], s1);
-    s2 = fmaf(wk, Z[zpos<PK>(i, 2, k, K)], s2);
+    s0 = fmaf(wk, Z[zpos<false>(i, 0, k, K)], s0);
+    s1 = fmaf(wk, Z[zpos<false>(i, 1, k, K)], s1);
+    s2 = fmaf(wk, Z[zpos<false>(i, 2, k, K)], s2);
   }
   for (int off = 32; off > 0; off >>= 1) {
     s0 += __shfl_xor(s0, off);
@@ -223,17 +222,21 @@ __global__ void __launch_bounds__(256) di_output_layer(int n, int K, const float
 // Packed path: one workgroup per node, each thread a set of K-groups of 8;
 // the node's three rows of a group are six float4s of the operand order and
 // the two output rows two float4s each.
-__global__ void __launch_bounds__(256) di_output_packed(int n, int K, const float* __restrict__ W,
-                                                        const float* __restrict__ b, const float* __restrict__ Z,
-                                                        float* __restrict__ y, float* __restrict__ J) {
-  __shared__ float red[6][4];
+constexpr int kOutThreads = 1024;  // one K-group per thread at width 8192: all loads in flight at once
+
+__global__ void __launch_bounds__(kOutThreads) di_output_packed(int n, int K, const float* __restrict__ W,
+                                                                const float* __restrict__ b,
+                                                                const float* __restrict__ Z, float* __restrict__ y,
+                                                                float* __restrict__ J) {
+  constexpr int NWV = kOutThreads / kWave;
+  __shared__ float red[6][NWV];
   const int i = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int G = K >> 3, tile = i / kNodesPerTile, r0 = 3 * (i - tile * kNodesPerTile);
   const float4* z4 = reinterpret_cast<const float4*>(Z) + (size_t)tile * G * 64;
   const float4* w0 = reinterpret_cast<const float4*>(W);
   const float4* w1 = reinterpret_cast<const float4*>(W + K);
   float s[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-  for (int j = t; j < G; j += 256) {
+  for (int j = t; j < G; j += kOutThreads) {
     const float4 a0 = w0[2 * j], a1 = w0[2 * j + 1], c0 = w1[2 * j], c1 = w1[2 * j + 1];
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
@@ -252,7 +255,8 @@ __global__ void __launch_bounds__(256) di_output_packed(int n, int K, const floa
   }
   __syncthreads();
   if (t < 6) {
-    const float v = red[t][0] + red[t][1] + red[t][2] + red[t][3];
+    float v = 0.f;
+    for (int w = 0; w < NWV; ++w) v += red[t][w];
     const int jo = t / 3, w = t % 3;
     if (w == 0) y[2 * i + jo] = v + b[jo];
     else J[(2 * i + jo) * 2 + (w - 1)] = v;
@@ -618,9 +622,9 @@ hipError_t launch_di_output_layer(int n, int K, const float* W, const float* b, 
                                   hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (di_packed(K))
-    di_output_packed<<<n, 256, 0, st>>>(n, K, W, b, Z, y, J);
+    di_output_packed<<<n, kOutThreads, 0, st>>>(n, K, W, b, Z, y, J);
   else
-    di_output_layer<false><<<2 * n, 256, 0, st>>>(n, K, W, b, Z, y, J);
+    di_output_layer<<<2 * n, 256, 0, st>>>(n, K, W, b, Z, y, J);
   return hipGetLastError();
 }
 

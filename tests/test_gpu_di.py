@@ -182,6 +182,26 @@ def test_di_rti_small_networks(torch, L, H, offsets):
     check_rti(res, data, offsets, MLP(Ws, bs))
 
 
+@pytest.mark.parametrize("H", [32, 256])
+def test_di_rti_many_instances(torch, H):
+    """300 instances with ragged horizons (1..30 nodes) in one call, on the
+    single-workgroup path (width 32) and on the layer kernels (width 256)."""
+    rng = np.random.default_rng(H)
+    horizons = rng.integers(1, 31, size=300)
+    offsets = np.concatenate([[0], np.cumsum(horizons)])
+    Ws, bs = di_net(3, H, seed=H + 5)
+    res, data = run_rti(torch, Ws, bs, offsets, seed=7)
+    check_rti(res, data, offsets, MLP(Ws, bs))
+
+
+def test_di_empty_batch(torch):
+    import paper_2203_07747_amd as rtn
+    x = torch.zeros((0, 2), device="cuda")
+    u = torch.zeros((0,), device="cuda")
+    out = rtn.di_linearize(x, u, None, DT)
+    assert out["A"].shape == (0, 2, 2)
+
+
 def test_di_rti_graph_replay_sees_new_data(torch):
     """Repeated calls replay one captured graph; new values in the same buffers are used."""
     import paper_2203_07747_amd as rtn

@@ -206,7 +206,9 @@ def extras(torch, rtn, lin_out, off, stream):
         xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
         out = {}
         f = lambda: rtn.linearize(xt, ut, m, "fp32", cfg.dt, offsets=o, out=out, stream=stream)
-        ms, wall = time_steps(torch, f, 200, 20, stream, warm_s=0.05)
+        ms_py, _ = time_steps(torch, f, 200, 20, stream, warm_s=0.05)
+        call = rtn.LinearizeCall(xt, ut, m, "fp32", cfg.dt, offsets=o, stream=stream)
+        ms, wall = time_steps(torch, call, 200, 20, stream, warm_s=0.05)
         rtn.profile_enable(True)
         for _ in range(20):
             f()
@@ -214,6 +216,7 @@ def extras(torch, rtn, lin_out, off, stream):
         kern = rtn.profile_collect()
         rtn.profile_enable(False)
         res[f"latency_{key}"] = {"workload": cfg.name, "us_per_call": ms * 1e3, "host_us_per_call": wall * 1e3,
+                                 "us_per_call_unprepared_python_call": ms_py * 1e3,
                                  "tile_choice": tile_choice(rtn, "fp32", cfg.width, cfg.n_hidden, x.shape[0]),
                                  "kernel_us_unbatched": {k: v["avg_ms"] * 1e3 for k, v in kern.items()}}
         m.close()

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, INPUT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "DiModel", "DiRtiCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "DiModel", "DiRtiCall", "LinearizeCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -271,6 +271,40 @@ def linearize(x, u, model: Optional[Model] = None, prec: str = "fp32", dt: float
                                _dev(st, torch.uint8, (n,), "status") if st is not None else None,
                                _stream(stream)), "rtn_linearize")
     return out
+
+
+class LinearizeCall:
+    """rtn_linearize with its arguments checked and marshalled once: each call only
+    enqueues the linearisation (the library replays its captured graph), for
+    real-time loops that refill the same x, u tensors every tick."""
+
+    def __init__(self, x, u, model: Optional[Model] = None, prec: str = "fp32", dt: float = 0.05, quad=None,
+                 offsets: Optional[np.ndarray] = None, want_fd: bool = True, want_status: bool = False,
+                 stream=None):
+        self.out = linearize(x, u, model, prec, dt, quad, offsets, want_fd, want_status, stream=stream)
+        torch = _torch()
+        from workload import QUAD
+        self._q = quad_struct(quad if quad is not None else QUAD)
+        n = x.shape[0]
+        self._off = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst = 1 if self._off is None else self._off.size - 1
+        o = self.out
+        f32 = torch.float32
+        self._fn = load().rtn_linearize
+        self._args = (model.handle if model is not None else None, PREC[prec], ctypes.byref(self._q),
+                      ctypes.c_float(dt), n_inst,
+                      None if self._off is None else self._off.ctypes.data_as(ctypes.c_void_p), n,
+                      _dev(x, f32, (n, 13), "x"), _dev(u, f32, (n, 4), "u"), _dev(o["x_next"], f32, (n, 13), "x_next"),
+                      _dev(o["A"], f32, (n, 13, 13), "A"), _dev(o["B"], f32, (n, 13, 4), "B"),
+                      _dev(o.get("f_D"), f32, (n, 6), "f_D"), _dev(o.get("J_D"), f32, (n, 6, 14), "J_D"),
+                      _dev(o.get("status"), torch.uint8, (n,), "status"), _stream(stream))
+        self._tensors = (x, u, model)  # keep the buffers alive
+
+    def __call__(self) -> Dict[str, object]:
+        code = self._fn(*self._args)
+        if code != 0:
+            check(code, "rtn_linearize")
+        return self.out
 
 
 def linearize_exact(x, u, model: Model, prec: str = "fp32", dt: float = 0.05, quad=None,

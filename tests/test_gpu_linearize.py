@@ -352,3 +352,25 @@ def test_small_batch_path_matches_oracle(torch, H, L, n):
     finally:
         rtn.tune_set("fp32", H, L, n, (0, 0, 0, 0, 0))
         m.close()
+
+
+def test_prepared_call_matches_and_sees_new_data(torch):
+    """LinearizeCall marshals once; later calls use the current contents of x, u."""
+    import paper_2203_07747_amd as rtn
+    cfg, off, x, u, Ws, bs = config_workload("c1")
+    m = rtn.Model(Ws, bs)
+    xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
+    call = rtn.LinearizeCall(xt, ut, m, "fp32", cfg.dt, offsets=off)
+    for seed in (1, 2):
+        x2, u2 = sample_nodes(x.shape[0], seed=seed)
+        xt.copy_(torch.from_numpy(x2))
+        ut.copy_(torch.from_numpy(u2))
+        print(f"[gpu] prepared linearize call, seed {seed}", flush=True)
+        out = call()
+        ref = rtn.linearize(xt, ut, m, "fp32", cfg.dt, offsets=off)
+        torch.cuda.synchronize()
+        for k in ("x_next", "A", "B", "f_D", "J_D"):
+            np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k].cpu().numpy())
+        check_against({k: v.cpu().numpy() for k, v in out.items()}, linearize_affine(x2, u2, MLP(Ws, bs), cfg.dt),
+                      1e-5)
+    m.close()

@@ -12,10 +12,15 @@
 //             G_{l-1} = (G_l W_l) (.) act'(a_{l-1});  J_D = G_1 W_1
 // Weights are the fp32 master copy, row-major [fan_out][fan_in]; activations,
 // derivatives and cotangents are row-major [rows][width] in model workspace.
+// Width-64 networks of at most 4 hidden layers take one fused launch instead,
+// with every operand in LDS (lat_fused_kernel).
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 
 #include "common.h"
 #include "mlp_chain.h"
+#include "rk4_node.h"
 
 namespace rtn {
 
@@ -213,6 +218,233 @@ hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* 
   }
   p.A = g + (size_t)(1 & 1) * M * H;
   return lat_launch<LA_ACT, LB_NN, LE_NONE>(p, st);
+}
+
+// ---------------------------------------------------------------------------
+// Small networks (width 64, at most 4 hidden layers): the forward pass, the
+// reverse sweep and J_D of up to 16 nodes in one workgroup -- one launch
+// instead of 2L + 1.  Every weight is staged into LDS once (odd row strides, so
+// that the column reads of the forward products are conflict free); products run
+// on MFMA 16x16x4 fp32, where lane l supplies row / column l % 16 at
+// k = 4 s + l / 16 and accumulator v of lane l is element (4 (l / 16) + v, l % 16).
+// With rk4 given, the same workgroup then takes its nodes through the RK4 step
+// (value, Jacobian and node data handed over in LDS).
+constexpr int kFzNodes = 16, kFzH = 64, kFzMaxL = 4, kFzThreads = 512;
+constexpr int kFzS = kFzH + 1, kFzW0S = kDin + 1, kFzRows = kFzNodes * kDout;  // 96 cotangent rows
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+static_assert(kFzNodes == kNodesPerBlock, "one RK4 block per workgroup");
+
+static size_t fz_lds_bytes(int L) {
+  const size_t f = (size_t)kFzH * kFzW0S + (size_t)(L - 1) * kFzH * kFzS + kDout * kFzH + L * kFzH + 8 +
+                   2 * kFzNodes * kFzS + (size_t)L * kFzNodes * kFzS + 2 * kFzRows * kFzS +
+                   kNodesPerBlock * kNodeStride + kNodesPerBlock;
+  return f * sizeof(float);
+}
+
+__device__ inline float fz_act(float a, int act, float* d) {
+  if (act == 0) {
+    const float sg = 1.f / (1.f + __expf(-a));
+    *d = sg * (1.f + a * (1.f - sg));
+    return a * sg;
+  }
+  *d = 1.f;
+  return a;
+}
+
+__global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n, const float* __restrict__ x,
+                                                               const float* __restrict__ u, float* __restrict__ y,
+                                                               float* __restrict__ J, FusedRk4 rk) {
+  extern __shared__ float lds[];
+  const int L = net.L;
+  float* w0 = lds;                         // W_1 [64][14], row stride 15
+  float* wh = w0 + kFzH * kFzW0S;          // W_2..W_L [64][64], row stride 65
+  float* wo = wh + (L - 1) * kFzH * kFzS;  // W_{L+1} [6][64]
+  float* bs = wo + kDout * kFzH;           // b_1..b_L [64] each, then b_{L+1} [6]
+  float* zf = bs + L * kFzH + 8;           // 2 x [16][65] activations (node rows)
+  float* spd = zf + 2 * kFzNodes * kFzS;   // L x [16][65] act'(a_l)
+  float* gb = spd + L * kFzNodes * kFzS;   // 2 x [96][65] cotangents, row (node, output)
+  float* rs = gb + 2 * kFzRows * kFzS;     // RK4 node data [16][kNodeStride], then 16 flags
+  const bool with_rk4 = rk.xn != nullptr;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, r = lane & 15, kq = lane >> 4;
+  const int node0 = blockIdx.x * kFzNodes, nn = min(kFzNodes, n - node0);
+
+  // every parameter in one flat index space, 16 loads in flight per thread
+  {
+    constexpr int nW0 = kFzH * kDin, nWh = kFzH * kFzH;
+    const int total = nW0 + (L - 1) * nWh + kDout * kFzH + L * kFzH + kDout;
+    for (int e0 = t; e0 < total; e0 += 16 * kFzThreads) {
+      float v[16];
+      int d[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e = e0 + i * kFzThreads;
+        d[i] = -1;
+        if (e >= total) continue;
+        const float* src;
+        if (e < nW0) {
+          const int row = e / kDin;
+          src = net.W[0] + e;
+          d[i] = row * kFzW0S + (e - row * kDin);
+        } else if (e < nW0 + (L - 1) * nWh) {
+          const int f = e - nW0, l = f / nWh, g = f - l * nWh;
+          src = net.W[l + 1] + g;
+          d[i] = (int)(wh - lds) + l * kFzH * kFzS + (g >> 6) * kFzS + (g & 63);
+        } else if (e < nW0 + (L - 1) * nWh + kDout * kFzH) {
+          const int f = e - nW0 - (L - 1) * nWh;
+          src = net.W[L] + f;
+          d[i] = (int)(wo - lds) + f;
+        } else {
+          const int f = e - nW0 - (L - 1) * nWh - kDout * kFzH;
+          src = net.b[f >> 6] + (f & 63);
+          d[i] = (int)(bs - lds) + f;
+        }
+        v[i] = *src;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (d[i] >= 0) lds[d[i]] = v[i];
+    }
+  }
+  for (int e = t; e < kFzNodes * kDin; e += kFzThreads) {
+    const int q = e / kDin, k = e - q * kDin;
+    zf[q * kFzS + k] =
+        q < nn ? net_feature(x + (size_t)(node0 + q) * kNx, u + (size_t)(node0 + q) * kNu, k, net.input) : 0.f;
+  }
+  if (with_rk4) {
+    for (int e = t; e < nn * kNx; e += kFzThreads)
+      rs[(e / kNx) * kNodeStride + e % kNx] = x[(size_t)node0 * kNx + e];
+    for (int e = t; e < nn * kNu; e += kFzThreads)
+      rs[(e / kNu) * kNodeStride + 13 + e % kNu] = u[(size_t)node0 * kNu + e];
+  }
+  __syncthreads();
+
+  // forward: a_l = h_{l-1} W_l^T + b_l, h_l = act(a_l); wave w < 4 owns columns 16 w .. 16 w + 15
+  int cur = 0;
+  for (int l = 0; l < L; ++l) {
+    if (wave < 4) {
+      const int c = wave * 16 + r;
+      const float* zin = zf + cur * kFzNodes * kFzS;
+      f32x4 acc = {};
+      if (l == 0) {
+#pragma unroll
+        for (int st = 0; st < (kDin + 3) / 4; ++st) {
+          const int k = 4 * st + kq;
+          const float a = k < kDin ? zin[r * kFzS + k] : 0.f;
+          const float b = k < kDin ? w0[c * kFzW0S + k] : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+      } else {
+        const float* W = wh + (l - 1) * kFzH * kFzS;
+#pragma unroll
+        for (int st = 0; st < kFzH / 4; ++st) {
+          const int k = 4 * st + kq;
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(zin[r * kFzS + k], W[c * kFzS + k], acc, 0, 0, 0);
+        }
+      }
+      float* zout = zf + (cur ^ 1) * kFzNodes * kFzS;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = 4 * kq + v;
+        float dd;
+        zout[q * kFzS + c] = fz_act(acc[v] + bs[l * kFzH + c], net.act, &dd);
+        spd[l * kFzNodes * kFzS + q * kFzS + c] = dd;
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // value y = W_{L+1} h_L + b_{L+1}; cotangent rows G_L[(q, j)] = W_{L+1}[j] (.) act'(a_L)[q]
+  const float* hL = zf + cur * kFzNodes * kFzS;
+  if (t < nn * kDout) {
+    const int q = t / kDout, j = t - q * kDout;
+    float sacc = bs[L * kFzH + j];
+    for (int k = 0; k < kFzH; ++k) sacc = fmaf(wo[j * kFzH + k], hL[q * kFzS + k], sacc);
+    y[(size_t)node0 * kDout + t] = sacc;
+    rs[q * kNodeStride + 17 + j] = sacc;
+  }
+  const int rows = nn * kDout, nrt = (rows + 15) / 16;
+  for (int e = t; e < nrt * 16 * kFzH; e += kFzThreads) {
+    const int p = e >> 6, k = e & 63, q = p / kDout, j = p - q * kDout;
+    gb[p * kFzS + k] = p < rows ? wo[j * kFzH + k] * spd[(L - 1) * kFzNodes * kFzS + q * kFzS + k] : 0.f;
+  }
+  __syncthreads();
+
+  // reverse: G_{l-1} = (G_l W_l) (.) act'(a_{l-1}); wave w owns column tile w % 4 and
+  // row tiles w / 4, w / 4 + 2, w / 4 + 4 (W_l read once for all of them)
+  int gc = 0;
+  for (int l = L - 1; l >= 1; --l) {
+    const float* W = wh + (l - 1) * kFzH * kFzS;
+    const float* gin = gb + gc * kFzRows * kFzS;
+    float* gout = gb + (gc ^ 1) * kFzRows * kFzS;
+    const int ct = wave & 3, rt0 = wave >> 2, c = ct * 16 + r;
+    f32x4 acc[3] = {};
+#pragma unroll 4
+    for (int st = 0; st < kFzH / 4; ++st) {
+      const int k = 4 * st + kq;
+      const float b = W[k * kFzS + c];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (rt0 + 2 * i < nrt)
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(gin[((rt0 + 2 * i) * 16 + r) * kFzS + k], b, acc[i], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (rt0 + 2 * i >= nrt) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = (rt0 + 2 * i) * 16 + 4 * kq + v, q = p / kDout;
+        gout[p * kFzS + c] = p < rows ? acc[i][v] * spd[(l - 1) * kFzNodes * kFzS + q * kFzS + c] : 0.f;
+      }
+    }
+    __syncthreads();
+    gc ^= 1;
+  }
+
+  // J_D = G_1 W_1 ([rows][64] x [64][14]): wave w < nrt owns row tile w
+  if (wave < nrt) {
+    const float* gin = gb + gc * kFzRows * kFzS;
+    f32x4 acc = {};
+#pragma unroll
+    for (int st = 0; st < kFzH / 4; ++st) {
+      const int k = 4 * st + kq;
+      const float b = r < kDin ? w0[k * kFzW0S + r] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gin[(wave * 16 + r) * kFzS + k], b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = wave * 16 + 4 * kq + v;
+      if (p < rows && r < kDin) {
+        J[((size_t)node0 * kDout + p) * kDin + r] = acc[v];
+        rs[(p / kDout) * kNodeStride + 23 + (p % kDout) * kDin + r] = acc[v];
+      }
+    }
+  }
+  if (with_rk4)  // uniform; the routine's first barrier publishes rs
+    rk4_block(rs, reinterpret_cast<int*>(rs + kNodesPerBlock * kNodeStride), nn, node0, t, rk.P, rk.dt, true, rk.xn,
+              rk.A, rk.B, rk.status, net.input);
+}
+
+bool lat_fused_fits(const LatNet& net) { return net.H == kFzH && net.L >= 1 && net.L <= kFzMaxL; }
+
+hipError_t launch_lat_fused(const LatNet& net, int n, const float* x, const float* u, float* y, float* J,
+                            hipStream_t st, const FusedRk4* rk4) {
+  if (n <= 0) return hipSuccess;
+  if (!lat_fused_fits(net)) return hipErrorInvalidValue;
+  static std::atomic<unsigned long long> lds_set{0};  // devices (id < 64) whose LDS limit is raised
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 64 || !(lds_set.load() >> dev & 1)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(lat_fused_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fz_lds_bytes(kFzMaxL));
+    if (e != hipSuccess) return e;
+    if (dev < 64) lds_set.fetch_or(1ull << dev);
+  }
+  lat_fused_kernel<<<(n + kFzNodes - 1) / kFzNodes, kFzThreads, fz_lds_bytes(net.L), st>>>(net, n, x, u, y, J,
+                                                                                     rk4 ? *rk4 : FusedRk4{});
+  return hipGetLastError();
 }
 
 // Tangents T_l = d a_l / d z_0 (14 rows per node, row (node, c) holds column c of

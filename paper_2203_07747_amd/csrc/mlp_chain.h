@@ -67,6 +67,10 @@ hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st)
 
 // Small-batch per-layer path (layer_lat.hip), fp32 master weights: W[l] is
 // W_{l+1} row-major [fan_out][fan_in], W[L] the output layer.
+struct QuadConst {
+  float mass, Jx, Jy, Jz, arm, c_tau, g;
+};
+
 struct LatNet {
   int L, H, act, input;
   const float* W[17];
@@ -81,14 +85,25 @@ hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const fl
 hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* g, float* J, hipStream_t st,
                               float* adj = nullptr);
 hipError_t launch_lat_tangent(const LatNet& net, int n, int l, const float* sp, float* tan, hipStream_t st);
+// Width 64 and <= 4 hidden layers: value y [n][6] and Jacobian J [n][6][14] in one
+// launch (16 nodes per workgroup, every operand in LDS); with rk4 given, the RK4
+// step of launch_rk4_linearize follows in the same launch.
+struct FusedRk4 {
+  QuadConst P;
+  float dt;
+  float* xn;  // nullptr: network only
+  float* A;
+  float* B;
+  uint8_t* status;  // nullable
+};
+bool lat_fused_fits(const LatNet& net);
+hipError_t launch_lat_fused(const LatNet& net, int n, const float* x, const float* u, float* y, float* J,
+                            hipStream_t st, const FusedRk4* rk4 = nullptr);
 // H_D [n][6][14][14] (+)= T_l^T diag(dy/dh_l (.) act''(a_l)) T_l for layer l (0-based);
 // T_0 = W_1, dy/dh_{L-1} = W_{L+1}; accumulate = 0 for the first layer visited.
 hipError_t launch_hess_accumulate(const LatNet& net, int n, int l, const float* tan, const float* adj,
                                   const float* spp, float* Hd, int accumulate, hipStream_t st);
 
-struct QuadConst {
-  float mass, Jx, Jy, Jz, arm, c_tau, g;
-};
 hipError_t launch_rk4_quadratic(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
                                 const float* JD, const float* HD, float* xn, float* A, float* B, hipStream_t st);
 // input: network input variant of JD's columns (0 full; 1, 2 body velocity)

@@ -505,6 +505,11 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
   if (tc.path == 1 && !lat_ok) tc = TuneChoice();  // an entry of this size class made for fewer nodes
   auto enqueue = [&](hipStream_t q) -> hipError_t {
     hipError_t e;
+    if (tc.path == 1 && lat_fused_fits(lv)) {  // small network: value, Jacobian and RK4 in one launch
+      const FusedRk4 rk{qc, dt, x_next, A, B, status};
+      ProfScope ps("lat_fused_rk4", q);
+      return launch_lat_fused(lv, n_nodes, x, u, y, J, q, &rk);
+    }
     if (tc.path == 1) {
       {
         ProfScope ps("lat_forward", q);

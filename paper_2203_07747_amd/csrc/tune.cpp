@@ -233,8 +233,12 @@ hipError_t tune_run(int prec, int H, const NetView& net, int n, const float* x, 
   if (err == hipSuccess && lat && prec == P_FP32 && n <= kLatMaxNodes) {
     float lf = 0.f, lr = 0.f;
     float* sp = static_cast<float*>(stash);
-    err = time_launch([&] { return launch_lat_forward(*lat, n, x, u, lat_act, sp, y, st); }, &lf);
-    if (err == hipSuccess) err = time_launch([&] { return launch_lat_reverse(*lat, n, sp, lat_g, J, st); }, &lr);
+    if (lat_fused_fits(*lat)) {  // one launch for value and Jacobian (the form rtn_linearize runs)
+      err = time_launch([&] { return launch_lat_fused(*lat, n, x, u, y, J, st); }, &lf);
+    } else {
+      err = time_launch([&] { return launch_lat_forward(*lat, n, x, u, lat_act, sp, y, st); }, &lf);
+      if (err == hipSuccess) err = time_launch([&] { return launch_lat_reverse(*lat, n, sp, lat_g, J, st); }, &lr);
+    }
     if (err == hipSuccess && lf + lr < best_f + best_r) {
       best = TuneChoice();
       best.path = 1;

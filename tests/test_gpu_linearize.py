@@ -333,7 +333,9 @@ def test_autotuner_keeps_a_valid_choice_and_results_match(torch):
     m.close()
 
 
-@pytest.mark.parametrize("H,L,n", [(64, 2, 10), (64, 1, 7), (512, 4, 20), (256, 3, 45), (1024, 2, 33), (128, 5, 300)])
+# width 64 with <= 4 hidden layers takes the one-launch kernel (16 nodes per workgroup)
+@pytest.mark.parametrize("H,L,n", [(64, 2, 10), (64, 1, 7), (64, 3, 45), (64, 4, 100), (64, 2, 16), (64, 5, 33),
+                                   (512, 4, 20), (256, 3, 45), (1024, 2, 33), (128, 5, 300)])
 def test_small_batch_path_matches_oracle(torch, H, L, n):
     """The per-layer small-batch path (fp32), forced through the tuning table."""
     import paper_2203_07747_amd as rtn

@@ -71,9 +71,32 @@ __device__ inline float lat_b(const LatArgs& p, int bkind, int k, int c) {
   return bkind == LB_NT ? p.W[(size_t)c * p.K + k] : p.W[(size_t)k * p.N + c];
 }
 
-// One 32 x 32 output tile per workgroup; wave w reduces K-steps w, w + nw, ...
+// Four consecutive k of one operand row (VEC path: 16-byte aligned, k % 4 == 0).
+__device__ inline float4 lat_a4(const LatArgs& p, int akind, int r, int k) {
+  if (r >= p.M) return make_float4(0.f, 0.f, 0.f, 0.f);
+  if (akind == LA_ACT) return *reinterpret_cast<const float4*>(p.A + (size_t)r * p.K + k);
+  const int node = r / p.rpn, j = r - p.rpn * node;
+  const float4 g = *reinterpret_cast<const float4*>(p.gate_a + (size_t)node * p.K + k);
+  const float4 a = akind == LA_TGATE ? *reinterpret_cast<const float4*>(p.A + (size_t)r * p.K + k)
+                                     : *reinterpret_cast<const float4*>(p.wsrc + (size_t)j * p.wj + k);
+  return make_float4(a.x * g.x, a.y * g.y, a.z * g.z, a.w * g.w);
+}
+
+__device__ inline float4 lat_b4(const LatArgs& p, int bkind, int k, int c) {
+  if (c >= p.N) return make_float4(0.f, 0.f, 0.f, 0.f);
+  if (bkind == LB_NT) return *reinterpret_cast<const float4*>(p.W + (size_t)c * p.K + k);
+  const float* w = p.W + (size_t)k * p.N + c;
+  return make_float4(w[0], w[p.N], w[2 * (size_t)p.N], w[3 * (size_t)p.N]);
+}
+
+// One 32 x 32 output tile per workgroup, the K-steps split over its waves
 // (32x32x2 fp32 MFMA); partial tiles are summed in LDS in fixed wave order.
-template <int AK, int BK, int EP>
+// Scalar path: wave w takes steps w, w + nw, ..., step s covering k = 2 s, 2 s + 1.
+// VEC path (K % 8 == 0, aligned operands, a multiple of 4 steps per wave): the
+// two k slots of the product run over the two halves of K, and wave w takes a
+// contiguous run of steps, so that every lane reads its operand rows as float4
+// (the row-major operands are otherwise read one strided float per row).
+template <int AK, int BK, int EP, bool VEC>
 __global__ void __launch_bounds__(kLatWaves * kWave) lat_layer(LatArgs p) {
   __shared__ float part[kLatWaves][32 * 33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -85,17 +108,34 @@ __global__ void __launch_bounds__(kLatWaves * kWave) lat_layer(LatArgs p) {
   // are L2 hits whose latency, not bandwidth, bounds a layer at this size)
   constexpr int MAXS = 32;  // K-steps per wave: K <= 2 * 16 * 32 = 1024
   float av[MAXS], bv[MAXS];
+  if constexpr (VEC) {
+    const int S = ksteps / nw, kb = kh * (p.K >> 1) + wave * S;
 #pragma unroll
-  for (int i = 0; i < MAXS; ++i) {
-    const int s = wave + i * nw;
-    const int k = 2 * s + kh;
-    const bool live = s < ksteps;
-    av[i] = live ? lat_a(p, AK, r, k) : 0.f;
-    bv[i] = live ? lat_b(p, BK, k, c) : 0.f;
+    for (int j = 0; j < MAXS / 4; ++j) {
+      float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4;
+      if (4 * j < S) {
+        a4 = lat_a4(p, AK, r, kb + 4 * j);
+        b4 = lat_b4(p, BK, kb + 4 * j, c);
+      }
+      av[4 * j] = a4.x, av[4 * j + 1] = a4.y, av[4 * j + 2] = a4.z, av[4 * j + 3] = a4.w;
+      bv[4 * j] = b4.x, bv[4 * j + 1] = b4.y, bv[4 * j + 2] = b4.z, bv[4 * j + 3] = b4.w;
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+      if (i < S) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[i], acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+      const int s = wave + i * nw;
+      const int k = 2 * s + kh;
+      const bool live = s < ksteps;
+      av[i] = live ? lat_a(p, AK, r, k) : 0.f;
+      bv[i] = live ? lat_b(p, BK, k, c) : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+      if (wave + i * nw < ksteps) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[i], acc, 0, 0, 0);
   }
-#pragma unroll
-  for (int i = 0; i < MAXS; ++i)
-    if (wave + i * nw < ksteps) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[i], acc, 0, 0, 0);
   // accumulator register i of lane l: row (i/4)*8 + (l/32)*4 + i%4, column l%32
 #pragma unroll
   for (int i = 0; i < 16; ++i) part[wave][((i >> 2) * 8 + kh * 4 + (i & 3)) * 33 + (lane & 31)] = acc[i];
@@ -137,7 +177,16 @@ template <int AK, int BK, int EP> static hipError_t lat_launch(const LatArgs& p,
   if (nw > kLatWaves) nw = kLatWaves;
   if (nw < 1) nw = 1;
   dim3 grid((p.N + 31) / 32, (p.M + 31) / 32);
-  lat_layer<AK, BK, EP><<<grid, nw * kWave, 0, st>>>(p);
+  auto al16 = [](const void* q) { return q == nullptr || reinterpret_cast<uintptr_t>(q) % 16 == 0; };
+  const bool vec = p.K % 8 == 0 && ksteps % nw == 0 && (ksteps / nw) % 4 == 0 && al16(p.A) && al16(p.gate_a) &&
+                   al16(p.W) && (AK != LA_GOUT || (p.wk == 1 && p.wj % 4 == 0 && al16(p.wsrc)));
+  if constexpr (AK != LA_Z0) {  // the input features are formed, not loaded
+    if (vec) {
+      lat_layer<AK, BK, EP, true><<<grid, nw * kWave, 0, st>>>(p);
+      return hipGetLastError();
+    }
+  }
+  lat_layer<AK, BK, EP, false><<<grid, nw * kWave, 0, st>>>(p);
   return hipGetLastError();
 }
 

@@ -536,14 +536,15 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
     ProfScope ps("rk4_linearize", q);
     return launch_rk4_linearize(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q, m->input);
   };
-  // The three launches are captured once per distinct argument set into a HIP
+  // The launches are captured once per distinct argument set into a HIP
   // graph (on a private stream) and replayed as one graph launch on the caller's
   // stream.  Profiling, or RTN_NO_GRAPH=1, uses plain launches.
   static const bool no_graph = [] {
     const char* e = getenv("RTN_NO_GRAPH");
     return e && e[0] == '1';
   }();
-  if (no_graph || profiling_on()) {
+  // A single launch (the fused small-network path) gains nothing from a graph.
+  if (no_graph || profiling_on() || (tc.path == 1 && lat_fused_fits(lv))) {
     HIP_TRY(enqueue(st));
     return RTN_OK;
   }

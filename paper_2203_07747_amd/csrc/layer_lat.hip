@@ -301,6 +301,35 @@ __device__ inline float fz_act(float a, int act, float* d) {
   return a;
 }
 
+// acc[i] += A_i (16 x 64) B (64 x 16) on MFMA 16x16x4 fp32: lane (r, kq) supplies
+// A_i[r][k] = ap[i][k - kq] (times gp[i][k - kq] when gated) and B[k][c] =
+// bp[(k - kq) bk] for k = 4 st + kq; every operand is read from LDS before the
+// first product.
+template <int NT, bool GATE = false>
+__device__ inline void fz_k64(const float* const* ap, const float* bp, int bk, f32x4* acc,
+                              const float* const* gp = nullptr) {
+  float a[NT][kFzH / 4], b[kFzH / 4];
+#pragma unroll
+  for (int st = 0; st < kFzH / 4; ++st) {
+    b[st] = bp[4 * st * bk];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) a[i][st] = GATE ? ap[i][4 * st] * gp[i][4 * st] : ap[i][4 * st];
+  }
+#pragma unroll
+  for (int st = 0; st < kFzH / 4; ++st)
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][st], b[st], acc[i], 0, 0, 0);
+}
+
+template <int NT>
+__device__ inline void fz_k64_any(bool gate, const float* const* ap, const float* bp, int bk, f32x4* acc,
+                                  const float* const* gp) {
+  if (gate)
+    fz_k64<NT, true>(ap, bp, bk, acc, gp);
+  else
+    fz_k64<NT, false>(ap, bp, bk, acc);
+}
+
 __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n, const float* __restrict__ x,
                                                                const float* __restrict__ u, float* __restrict__ y,
                                                                float* __restrict__ J, FusedRk4 rk) {
@@ -318,53 +347,53 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, r = lane & 15, kq = lane >> 4;
   const int node0 = blockIdx.x * kFzNodes, nn = min(kFzNodes, n - node0);
 
-  // every parameter in one flat index space, 16 loads in flight per thread
+  // every parameter and the block's x, u: all loads issued first (clamped indices,
+  // so that every address is valid and no load sits under a branch), then stored
   {
-    constexpr int nW0 = kFzH * kDin, nWh = kFzH * kFzH;
-    const int total = nW0 + (L - 1) * nWh + kDout * kFzH + L * kFzH + kDout;
-    for (int e0 = t; e0 < total; e0 += 16 * kFzThreads) {
-      float v[16];
-      int d[16];
+    constexpr int nW0 = kFzH * kDin, nWh = kFzH * kFzH, nHi = nWh / kFzThreads;
+    static_assert(nWh % kFzThreads == 0 && 2 * kFzThreads >= nW0 && kFzThreads >= kDout * kFzH &&
+                      kFzThreads >= kFzMaxL * kFzH + kDout && kFzThreads >= kFzNodes * kNx,
+                  "staging covers every parameter in one pass");
+    const float* W0 = net.W[0];
+    float v0[2], vh[kFzMaxL - 1][nHi];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int e = e0 + i * kFzThreads;
-        d[i] = -1;
-        if (e >= total) continue;
-        const float* src;
-        if (e < nW0) {
-          const int row = e / kDin;
-          src = net.W[0] + e;
-          d[i] = row * kFzW0S + (e - row * kDin);
-        } else if (e < nW0 + (L - 1) * nWh) {
-          const int f = e - nW0, l = f / nWh, g = f - l * nWh;
-          src = net.W[l + 1] + g;
-          d[i] = (int)(wh - lds) + l * kFzH * kFzS + (g >> 6) * kFzS + (g & 63);
-        } else if (e < nW0 + (L - 1) * nWh + kDout * kFzH) {
-          const int f = e - nW0 - (L - 1) * nWh;
-          src = net.W[L] + f;
-          d[i] = (int)(wo - lds) + f;
-        } else {
-          const int f = e - nW0 - (L - 1) * nWh - kDout * kFzH;
-          src = net.b[f >> 6] + (f & 63);
-          d[i] = (int)(bs - lds) + f;
-        }
-        v[i] = *src;
-      }
+    for (int i = 0; i < 2; ++i) v0[i] = W0[min(t + i * kFzThreads, nW0 - 1)];
 #pragma unroll
-      for (int i = 0; i < 16; ++i)
-        if (d[i] >= 0) lds[d[i]] = v[i];
+    for (int l = 0; l < kFzMaxL - 1; ++l) {
+      const bool live = l + 1 < L;  // uniform
+      const float* src = live ? net.W[l + 1] : W0;
+#pragma unroll
+      for (int i = 0; i < nHi; ++i) vh[l][i] = src[live ? t + i * kFzThreads : 0];
     }
+    const float vo = net.W[L][min(t, kDout * kFzH - 1)];
+    const int nb = L * kFzH + kDout, lb = t < nb ? t >> 6 : 0;
+    const float* bsrc = lb == 0 ? net.b[0] : lb == 1 ? net.b[1] : lb == 2 ? net.b[2] : lb == 3 ? net.b[3] : net.b[4];
+    const float vb = bsrc[t < nb ? t & 63 : 0];
+    const float vx = x[(size_t)node0 * kNx + min(t, nn * kNx - 1)];
+    const float vu = u[(size_t)node0 * kNu + min(t, nn * kNu - 1)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = t + i * kFzThreads, row = e / kDin;
+      if (e < nW0) w0[row * kFzW0S + (e - row * kDin)] = v0[i];
+    }
+#pragma unroll
+    for (int l = 0; l < kFzMaxL - 1; ++l)
+      if (l + 1 < L)
+#pragma unroll
+        for (int i = 0; i < nHi; ++i) {
+          const int e = t + i * kFzThreads;
+          wh[l * kFzH * kFzS + (e >> 6) * kFzS + (e & 63)] = vh[l][i];
+        }
+    if (t < kDout * kFzH) wo[t] = vo;
+    if (t < nb) bs[t] = vb;
+    if (t < nn * kNx) rs[(t / kNx) * kNodeStride + t % kNx] = vx;
+    if (t < nn * kNu) rs[(t >> 2) * kNodeStride + 13 + (t & 3)] = vu;
   }
-  for (int e = t; e < kFzNodes * kDin; e += kFzThreads) {
+  __syncthreads();
+  for (int e = t; e < kFzNodes * kDin; e += kFzThreads) {  // network input features from the staged x, u
     const int q = e / kDin, k = e - q * kDin;
-    zf[q * kFzS + k] =
-        q < nn ? net_feature(x + (size_t)(node0 + q) * kNx, u + (size_t)(node0 + q) * kNu, k, net.input) : 0.f;
-  }
-  if (with_rk4) {
-    for (int e = t; e < nn * kNx; e += kFzThreads)
-      rs[(e / kNx) * kNodeStride + e % kNx] = x[(size_t)node0 * kNx + e];
-    for (int e = t; e < nn * kNu; e += kFzThreads)
-      rs[(e / kNu) * kNodeStride + 13 + e % kNu] = u[(size_t)node0 * kNu + e];
+    const float* sn = rs + q * kNodeStride;
+    zf[q * kFzS + k] = q < nn ? net_feature(sn, sn + 13, k, net.input) : 0.f;
   }
   __syncthreads();
 
@@ -376,20 +405,18 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
       const float* zin = zf + cur * kFzNodes * kFzS;
       f32x4 acc = {};
       if (l == 0) {
+        float a[4], b[4];
 #pragma unroll
-        for (int st = 0; st < (kDin + 3) / 4; ++st) {
+        for (int st = 0; st < 4; ++st) {
           const int k = 4 * st + kq;
-          const float a = k < kDin ? zin[r * kFzS + k] : 0.f;
-          const float b = k < kDin ? w0[c * kFzW0S + k] : 0.f;
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+          a[st] = k < kDin ? zin[r * kFzS + k] : 0.f;
+          b[st] = k < kDin ? w0[c * kFzW0S + k] : 0.f;
         }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], b[st], acc, 0, 0, 0);
       } else {
-        const float* W = wh + (l - 1) * kFzH * kFzS;
-#pragma unroll
-        for (int st = 0; st < kFzH / 4; ++st) {
-          const int k = 4 * st + kq;
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(zin[r * kFzS + k], W[c * kFzS + k], acc, 0, 0, 0);
-        }
+        const float* ap[1] = {zin + r * kFzS + kq};
+        fz_k64<1>(ap, wh + (l - 1) * kFzH * kFzS + c * kFzS + kq, 1, &acc);
       }
       float* zout = zf + (cur ^ 1) * kFzNodes * kFzS;
 #pragma unroll
@@ -404,43 +431,37 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
     cur ^= 1;
   }
 
-  // value y = W_{L+1} h_L + b_{L+1}; cotangent rows G_L[(q, j)] = W_{L+1}[j] (.) act'(a_L)[q]
-  const float* hL = zf + cur * kFzNodes * kFzS;
-  if (t < nn * kDout) {
-    const int q = t / kDout, j = t - q * kDout;
-    float sacc = bs[L * kFzH + j];
-    for (int k = 0; k < kFzH; ++k) sacc = fmaf(wo[j * kFzH + k], hL[q * kFzS + k], sacc);
-    y[(size_t)node0 * kDout + t] = sacc;
-    rs[q * kNodeStride + 17 + j] = sacc;
-  }
+  // reverse: G_{l-1} = (G_l W_l) (.) act'(a_{l-1}), where the first operand G_L =
+  // W_{L+1} (.) act'(a_L) (row (q, j) = W_{L+1}[j] (.) act'(a_L)[q]) is formed while
+  // loading; wave w owns column tile w % 4 and row tiles w / 4, w / 4 + 2, w / 4 + 4
+  // below nrt (W_l read once for all of them)
   const int rows = nn * kDout, nrt = (rows + 15) / 16;
-  for (int e = t; e < nrt * 16 * kFzH; e += kFzThreads) {
-    const int p = e >> 6, k = e & 63, q = p / kDout, j = p - q * kDout;
-    gb[p * kFzS + k] = p < rows ? wo[j * kFzH + k] * spd[(L - 1) * kFzNodes * kFzS + q * kFzS + k] : 0.f;
-  }
-  __syncthreads();
-
-  // reverse: G_{l-1} = (G_l W_l) (.) act'(a_{l-1}); wave w owns column tile w % 4 and
-  // row tiles w / 4, w / 4 + 2, w / 4 + 4 (W_l read once for all of them)
+  const float* spL = spd + (L - 1) * kFzNodes * kFzS;
   int gc = 0;
   for (int l = L - 1; l >= 1; --l) {
-    const float* W = wh + (l - 1) * kFzH * kFzS;
+    const bool first = l == L - 1;
     const float* gin = gb + gc * kFzRows * kFzS;
-    float* gout = gb + (gc ^ 1) * kFzRows * kFzS;
-    const int ct = wave & 3, rt0 = wave >> 2, c = ct * 16 + r;
-    f32x4 acc[3] = {};
-#pragma unroll 4
-    for (int st = 0; st < kFzH / 4; ++st) {
-      const int k = 4 * st + kq;
-      const float b = W[k * kFzS + c];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        if (rt0 + 2 * i < nrt)
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(gin[((rt0 + 2 * i) * 16 + r) * kFzS + k], b, acc[i], 0, 0, 0);
-    }
+    float* gout = gb + (first ? 0 : gc ^ 1) * kFzRows * kFzS;
+    const int ct = wave & 3, rt0 = wave >> 2, c = ct * 16 + r, ntl = (nrt - rt0 + 1) / 2;  // uniform per wave
+    const float* ap[3];
+    const float* gp[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      if (rt0 + 2 * i >= nrt) continue;
+      const int p = (rt0 + 2 * i) * 16 + r, q = p / kDout;  // p < 96: q < 16
+      ap[i] = first ? wo + (p - q * kDout) * kFzH + kq : gin + p * kFzS + kq;
+      gp[i] = spL + q * kFzS + kq;
+    }
+    const float* bp = wh + (l - 1) * kFzH * kFzS + kq * kFzS + c;
+    f32x4 acc[3] = {};
+    if (ntl >= 3)
+      fz_k64_any<3>(first, ap, bp, kFzS, acc, gp);
+    else if (ntl == 2)
+      fz_k64_any<2>(first, ap, bp, kFzS, acc, gp);
+    else if (ntl == 1)
+      fz_k64_any<1>(first, ap, bp, kFzS, acc, gp);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (i >= ntl) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int p = (rt0 + 2 * i) * 16 + 4 * kq + v, q = p / kDout;
@@ -448,25 +469,37 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
       }
     }
     __syncthreads();
-    gc ^= 1;
+    gc = first ? 0 : gc ^ 1;
   }
 
-  // J_D = G_1 W_1 ([rows][64] x [64][14]): wave w < nrt owns row tile w
+  // J_D = G_1 W_1 ([rows][64] x [64][14]; G_1 = G_L formed on load when L = 1):
+  // wave w < nrt owns row tile w; wave 7 meanwhile forms y = W_{L+1} h_L + b_{L+1}
+  // (one 16 x 16 tile, 6 columns live)
   if (wave < nrt) {
-    const float* gin = gb + gc * kFzRows * kFzS;
+    const int p = wave * 16 + r, q = p / kDout;
+    const float* ap[1] = {L == 1 ? wo + (p - q * kDout) * kFzH + kq : gb + gc * kFzRows * kFzS + p * kFzS + kq};
+    const float* gp[1] = {spL + q * kFzS + kq};
     f32x4 acc = {};
-#pragma unroll
-    for (int st = 0; st < kFzH / 4; ++st) {
-      const int k = 4 * st + kq;
-      const float b = r < kDin ? w0[k * kFzW0S + r] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gin[(wave * 16 + r) * kFzS + k], b, acc, 0, 0, 0);
-    }
+    fz_k64_any<1>(L == 1, ap, w0 + kq * kFzW0S + r, kFzW0S, &acc, gp);  // columns r >= 14 are dropped
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int p = wave * 16 + 4 * kq + v;
-      if (p < rows && r < kDin) {
-        J[((size_t)node0 * kDout + p) * kDin + r] = acc[v];
-        rs[(p / kDout) * kNodeStride + 23 + (p % kDout) * kDin + r] = acc[v];
+      const int pv = wave * 16 + 4 * kq + v;
+      if (pv < rows && r < kDin) {
+        J[((size_t)node0 * kDout + pv) * kDin + r] = acc[v];
+        rs[(pv / kDout) * kNodeStride + 23 + (pv % kDout) * kDin + r] = acc[v];
+      }
+    }
+  } else if (wave == 7) {
+    const float* ap[1] = {zf + cur * kFzNodes * kFzS + r * kFzS + kq};
+    f32x4 acc = {};
+    fz_k64<1>(ap, wo + r * kFzH + kq, 1, &acc);  // columns r >= 6 read other LDS data and are dropped
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = 4 * kq + v;
+      if (q < nn && r < kDout) {
+        const float yv = acc[v] + bs[L * kFzH + r];
+        y[((size_t)node0 + q) * kDout + r] = yv;
+        rs[q * kNodeStride + 17 + r] = yv;
       }
     }
   }

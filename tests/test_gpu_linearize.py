@@ -140,6 +140,28 @@ def test_status_flags(torch):
     assert np.all(res["status"] & 1)
 
 
+@pytest.mark.parametrize("H,path", [(64, 1), (256, 1), (64, 0), (256, 0)])
+def test_status_flags_each_path(torch, H, path):
+    """Status bits from the one-launch small network kernel (width 64), the tail kernel
+    of the per-layer path (wider) and the layer-chain path, forced through the tuning table."""
+    import paper_2203_07747_amd as rtn
+    Ws, bs = xavier_params(2, H)
+    x, u = sample_nodes(21, seed=6)
+    x[17, 8] = np.nan
+    m = rtn.Model(Ws, bs)
+    try:
+        rtn.tune_set("fp32", H, 2, 21, (path, 0, 0, 0, 0))
+        print(f"[gpu] status flags H={H} path={path}", flush=True)
+        out = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), m, "fp32", DT, want_status=True)
+        torch.cuda.synchronize()
+        st = out["status"].cpu().numpy()
+    finally:
+        rtn.tune_set("fp32", H, 2, 21, (0, 0, 0, 0, 0))
+        m.close()
+    assert st[17] & 1 and st[17] & 2
+    assert np.all(st[np.arange(21) != 17] == 0)
+
+
 def test_bf16_matches_emulation_and_oracle(torch):
     Ws, bs = xavier_params(5, 512, seed=0)
     x, u = sample_nodes(2000, seed=1)
@@ -334,8 +356,10 @@ def test_autotuner_keeps_a_valid_choice_and_results_match(torch):
 
 
 # width 64 with <= 4 hidden layers takes the one-launch kernel (16 nodes per workgroup)
+# and wider ones (L >= 2) end in the tail kernel: n = 1 and a last block of one node included
 @pytest.mark.parametrize("H,L,n", [(64, 2, 10), (64, 1, 7), (64, 3, 45), (64, 4, 100), (64, 2, 16), (64, 5, 33),
-                                   (512, 4, 20), (256, 3, 45), (1024, 2, 33), (128, 5, 300)])
+                                   (512, 4, 20), (256, 3, 45), (1024, 2, 33), (128, 5, 300), (128, 2, 1),
+                                   (512, 2, 17), (256, 1, 12)])
 def test_small_batch_path_matches_oracle(torch, H, L, n):
     """The per-layer small-batch path (fp32), forced through the tuning table."""
     import paper_2203_07747_amd as rtn

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, INPUT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "DiModel", "DiRtiCall", "LinearizeCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "DiModel", "DiRtiCall", "LinearizeCall", "RiccatiCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -405,6 +405,33 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
                              _dev(P, f64, (n, 13, 13), "P") if P is not None else None,
                              _stream(stream)), "rtn_riccati")
     return out
+
+
+class RiccatiCall:
+    """rtn_riccati with its arguments checked and marshalled once (no affine terms):
+    each call only enqueues the recursion over the current contents of A, B."""
+
+    def __init__(self, A, B, Q, R, QN, offsets=None, want_P: bool = False, stream=None):
+        self.out = riccati(A, B, Q, R, QN, offsets=offsets, want_P=want_P, stream=stream)
+        torch = _torch()
+        n = A.shape[0]
+        self._off = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.int32)
+        n_inst = 1 if self._off is None else self._off.size - 1
+        self._h = [np.ascontiguousarray(M, dtype=np.float64) for M in (Q, R, QN)]
+        f64, o = torch.float64, self.out
+        self._fn = load().rtn_riccati
+        self._args = (n_inst, None if self._off is None else self._off.ctypes.data_as(ctypes.c_void_p), n,
+                      _dev(A, torch.float32, (n, 13, 13), "A"), _dev(B, torch.float32, (n, 13, 4), "B"), None,
+                      *(M.ctypes.data_as(ctypes.c_void_p) for M in self._h), None, None, None,
+                      _dev(o["K"], f64, (n, 4, 13), "K"), _dev(o["kff"], f64, (n, 4), "kff"),
+                      _dev(o.get("P"), f64, (n, 13, 13), "P"), _stream(stream))
+        self._tensors = (A, B)  # keep the buffers alive
+
+    def __call__(self) -> Dict[str, object]:
+        code = self._fn(*self._args)
+        if code != 0:
+            check(code, "rtn_riccati")
+        return self.out
 
 
 def riccati_box(A, B, Q, R, QN, dx0, du_lo, du_hi, offsets=None, c=None, q=None, r=None, qN=None,

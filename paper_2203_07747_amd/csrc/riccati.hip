@@ -7,9 +7,11 @@
 //   K   = -Quu^{-1} Qux,  kff = -Quu^{-1} qu               (Cholesky of the 4x4 Quu)
 //   P  <- sym(Qxx + Qux^T K),  p <- qx + Qux^T kff
 //
-// One 64-lane workgroup per instance; the 13x13 matrices live in LDS in fp64
-// and each lane owns a few of their entries.  The recursion is sequential in k,
-// so instances (not nodes) are the parallel axis.
+// One 64-lane workgroup per instance; the 13x13 matrices live in LDS in fp64.
+// The products (P A, P [B | c], A^T and B^T times those, Qux^T K) run on fp64
+// MFMA 16x16x4 with the matrices padded to 16 x 16; the 4x4 Cholesky solve on
+// the lanes.  The recursion is sequential in k, so instances (not nodes) are
+// the parallel axis.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -18,6 +20,7 @@
 namespace rtn {
 
 constexpr int NX = 13, NU = 4;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct RiccatiArgs {
   const int* offsets;   // [n_inst + 1]
@@ -35,12 +38,19 @@ struct RiccatiArgs {
   double* P;            // nullable [n][13][13]
 };
 
+// The recursion runs on one wave per workgroup: lanes exchange data through LDS,
+// whose operations a wave issues and completes in order, so a wait for those
+// (with a compiler memory barrier) orders them; __syncthreads would also wait for
+// the next node's global loads, which are meant to stay in flight.
+__device__ inline void wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 __global__ void __launch_bounds__(64) riccati_kernel(RiccatiArgs a) {
   __shared__ double sQ[NX * NX], sR[NU * NU];
   __shared__ double sA[NX * NX], sB[NX * NU], sP[NX * NX], sPA[NX * NX], sPB[NX * NU];
   __shared__ double sQxx[NX * NX], sQux[NU * NX], sQuu[NU * NU], sK[NU * NX];
   __shared__ double sc[NX], sp[NX], sg[NX], sqx[NX], squ[NU], skff[NU], sq[NX], sr[NU];
-  const int inst = blockIdx.x, t = threadIdx.x;
+  const int inst = blockIdx.x, t = threadIdx.x, r = t & 15, kq = t >> 4;
+  const int rc13 = min(r, NX - 1), rc4 = min(r, NU - 1);  // clamped: LDS reads stay unconditional
   const int k0 = a.offsets[inst], k1 = a.offsets[inst + 1];
   for (int i = t; i < NX * NX; i += 64) {
     sQ[i] = a.Q[i];
@@ -48,93 +58,137 @@ __global__ void __launch_bounds__(64) riccati_kernel(RiccatiArgs a) {
   }
   for (int i = t; i < NU * NU; i += 64) sR[i] = a.R[i];
   for (int i = t; i < NX; i += 64) sp[i] = a.qN ? a.qN[(size_t)inst * NX + i] : 0.0;
+  // node data is loaded into registers one step ahead, so that its global
+  // latency overlaps the previous node's arithmetic
+  float ra[3] = {}, rb = 0.f;
+  double rc = 0.0, rq = 0.0, rr = 0.0;
+  // (clamped indices and substitute addresses: every load is issued unconditionally,
+  // so that no wait is forced where divergent paths join)
+  const bool has_c = a.c != nullptr, has_q = a.q != nullptr, has_r = a.r != nullptr;
+  const double* cptr = has_c ? a.c : a.Q;
+  const double* qptr = has_q ? a.q : a.Q;
+  const double* rptr = has_r ? a.r : a.Q;
+  auto load_node = [&](int k) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) ra[j] = a.A[(size_t)k * NX * NX + min(t + 64 * j, NX * NX - 1)];
+    rb = a.B[(size_t)k * NX * NU + min(t, NX * NU - 1)];
+    rc = cptr[(has_c ? (size_t)k * NX : 0) + min(t, NX - 1)];
+    rq = qptr[(has_q ? (size_t)k * NX : 0) + min(t, NX - 1)];
+    rr = rptr[(has_r ? (size_t)k * NU : 0) + min(t, NU - 1)];
+  };
+  if (k1 > k0) load_node(k1 - 1);
   __syncthreads();
   for (int k = k1 - 1; k >= k0; --k) {
-    // stage the node's data (fp32 A, B promoted exactly)
-    for (int i = t; i < NX * NX; i += 64) sA[i] = (double)a.A[(size_t)k * NX * NX + i];
-    if (t < NX * NU) sB[t] = (double)a.B[(size_t)k * NX * NU + t];
+    // stage the node's data (fp32 A, B promoted exactly); the last barrier of the
+    // previous step ended every read of these buffers
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int i = t + 64 * j;
+      if (i < NX * NX) sA[i] = (double)ra[j];
+    }
+    if (t < NX * NU) sB[t] = (double)rb;
     if (t < NX) {
-      sc[t] = a.c ? a.c[(size_t)k * NX + t] : 0.0;
-      sq[t] = a.q ? a.q[(size_t)k * NX + t] : 0.0;
+      sc[t] = has_c ? rc : 0.0;
+      sq[t] = has_q ? rq : 0.0;
     }
-    if (t < NU) sr[t] = a.r ? a.r[(size_t)k * NU + t] : 0.0;
-    __syncthreads();
-    // P A, P B, g = P c + p
-    for (int e = t; e < NX * NX; e += 64) {
-      const int i = e / NX, j = e % NX;
-      double s = 0.0;
-      for (int m = 0; m < NX; ++m) s += sP[i * NX + m] * sA[m * NX + j];
-      sPA[e] = s;
+    if (t < NU) sr[t] = has_r ? rr : 0.0;
+    if (k > k0) load_node(k - 1);
+    wave_sync();
+    // P A, P [B | c] on fp64 MFMA 16x16x4 (13 x 13 padded to 16 x 16): lane (r, kq)
+    // supplies row / column r at k = 4 s + kq; accumulator v of the lane is element
+    // (kq + 4 v, r) (the fp64 form interleaves rows, unlike the fp32 one).  Column 4
+    // of the second product gives g = P c + p.
+    {
+      f64x4 dPA = {}, dPB = {};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 4 * s4 + kq, kc = min(k, NX - 1);
+        const bool kin = k < NX, rin = r < NX;
+        const double p0 = sP[rc13 * NX + kc], a0 = sA[kc * NX + rc13], b0 = sB[kc * NU + rc4], c0 = sc[kc];
+        const double pk = (rin && kin) ? p0 : 0.0;
+        const double ak = (rin && kin) ? a0 : 0.0;
+        const double bk = kin ? (r < NU ? b0 : (r == NU ? c0 : 0.0)) : 0.0;
+        dPA = __builtin_amdgcn_mfma_f64_16x16x4f64(pk, ak, dPA, 0, 0, 0);
+        dPB = __builtin_amdgcn_mfma_f64_16x16x4f64(pk, bk, dPB, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = kq + 4 * v;
+        const double spi = sp[min(i, NX - 1)];
+        if (i < NX) {
+          if (r < NX) sPA[i * NX + r] = dPA[v];
+          if (r < NU) sPB[i * NU + r] = dPB[v];
+          if (r == NU) sg[i] = dPB[v] + spi;
+        }
+      }
     }
-    if (t < NX * NU) {
-      const int i = t / NU, j = t % NU;
-      double s = 0.0;
-      for (int m = 0; m < NX; ++m) s += sP[i * NX + m] * sB[m * NU + j];
-      sPB[t] = s;
+    wave_sync();
+    // A^T and B^T times P A and [P B | g]: Qxx, qx, Qux, Quu, qu
+    {
+      f64x4 dQxx = {}, dAg = {}, dQux = {}, dBg = {};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 4 * s4 + kq, kc = min(k, NX - 1);
+        const bool kin = k < NX, rin = r < NX;
+        const double a0 = sA[kc * NX + rc13], b0 = sB[kc * NU + rc4], p0 = sPA[kc * NX + rc13], q0 = sPB[kc * NU + rc4],
+                     g0 = sg[kc];
+        const double at = (rin && kin) ? a0 : 0.0;      // A^T[r][k]
+        const double bt = (r < NU && kin) ? b0 : 0.0;   // B^T[r][k]
+        const double pa = (rin && kin) ? p0 : 0.0;      // (P A)[k][r]
+        const double pb = kin ? (r < NU ? q0 : (r == NU ? g0 : 0.0)) : 0.0;
+        dQxx = __builtin_amdgcn_mfma_f64_16x16x4f64(at, pa, dQxx, 0, 0, 0);
+        dAg = __builtin_amdgcn_mfma_f64_16x16x4f64(at, pb, dAg, 0, 0, 0);
+        dQux = __builtin_amdgcn_mfma_f64_16x16x4f64(bt, pa, dQux, 0, 0, 0);
+        dBg = __builtin_amdgcn_mfma_f64_16x16x4f64(bt, pb, dBg, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = kq + 4 * v, ic = min(i, NX - 1), i4 = min(i, NU - 1);
+        const double q0 = sQ[ic * NX + rc13], qv = sq[ic], r0 = sR[i4 * NU + rc4], rv = sr[i4];
+        if (i < NX && r < NX) sQxx[i * NX + r] = q0 + dQxx[v];
+        if (i < NX && r == NU) sqx[i] = qv + dAg[v];
+        if (i < NU && r < NX) sQux[i * NX + r] = dQux[v];
+        if (i < NU && r < NU) sQuu[i * NU + r] = r0 + dBg[v];
+        if (i < NU && r == NU) squ[i] = rv + dBg[v];
+      }
     }
-    if (t < NX) {
-      double s = sp[t];
-      for (int m = 0; m < NX; ++m) s += sP[t * NX + m] * sc[m];
-      sg[t] = s;
-    }
-    __syncthreads();
-    // Qxx, Qux, Quu, qx, qu
-    for (int e = t; e < NX * NX; e += 64) {
-      const int i = e / NX, j = e % NX;
-      double s = sQ[e];
-      for (int m = 0; m < NX; ++m) s += sA[m * NX + i] * sPA[m * NX + j];
-      sQxx[e] = s;
-    }
-    if (t < NU * NX) {
-      const int u = t / NX, j = t % NX;
-      double s = 0.0;
-      for (int m = 0; m < NX; ++m) s += sB[m * NU + u] * sPA[m * NX + j];
-      sQux[t] = s;
-    }
-    if (t < NU * NU) {
-      const int u = t / NU, v = t % NU;
-      double s = sR[t];
-      for (int m = 0; m < NX; ++m) s += sB[m * NU + u] * sPB[m * NU + v];
-      sQuu[t] = s;
-    }
-    if (t < NX) {
-      double s = sq[t];
-      for (int m = 0; m < NX; ++m) s += sA[m * NX + t] * sg[m];
-      sqx[t] = s;
-    }
-    if (t < NU) {
-      double s = sr[t];
-      for (int m = 0; m < NX; ++m) s += sB[m * NU + t] * sg[m];
-      squ[t] = s;
-    }
-    __syncthreads();
+    wave_sync();
     // K = -Quu^-1 Qux (columns 0..12), kff = -Quu^-1 qu (column 13): each lane
     // factors Quu = L L^T itself and solves its own right-hand side.
     if (t <= NX) {
-      double Lc[NU][NU] = {};
+      double Lc[NU][NU] = {}, il[NU];  // il: reciprocals of the diagonal (one division each)
       bool ok = true;
+#pragma unroll
       for (int j = 0; j < NU; ++j) {
         double d = sQuu[j * NU + j];
+#pragma unroll
         for (int m = 0; m < j; ++m) d -= Lc[j][m] * Lc[j][m];
         ok = ok && d > 0.0;
         const double ljj = sqrt(d);
         Lc[j][j] = ljj;
+        il[j] = 1.0 / ljj;
+#pragma unroll
         for (int i = j + 1; i < NU; ++i) {
           double s = 0.5 * (sQuu[i * NU + j] + sQuu[j * NU + i]);
+#pragma unroll
           for (int m = 0; m < j; ++m) s -= Lc[i][m] * Lc[j][m];
-          Lc[i][j] = s / ljj;
+          Lc[i][j] = s * il[j];
         }
       }
       double y[NU], x[NU];
+#pragma unroll
       for (int i = 0; i < NU; ++i) {
         double s = t < NX ? sQux[i * NX + t] : squ[i];
+#pragma unroll
         for (int m = 0; m < i; ++m) s -= Lc[i][m] * y[m];
-        y[i] = s / Lc[i][i];
+        y[i] = s * il[i];
       }
+#pragma unroll
       for (int i = NU - 1; i >= 0; --i) {
         double s = y[i];
+#pragma unroll
         for (int m = i + 1; m < NU; ++m) s -= Lc[m][i] * x[m];
-        x[i] = s / Lc[i][i];
+        x[i] = s * il[i];
       }
       const double nan = __builtin_nan("");
       for (int i = 0; i < NU; ++i) {
@@ -143,27 +197,33 @@ __global__ void __launch_bounds__(64) riccati_kernel(RiccatiArgs a) {
         else skff[i] = v;
       }
     }
-    __syncthreads();
+    wave_sync();
     // outputs of node k and the value function before it
     for (int e = t; e < NU * NX; e += 64) a.K[(size_t)k * NU * NX + e] = sK[e];
     if (t < NU) a.kff[(size_t)k * NU + t] = skff[t];
-    for (int e = t; e < NX * NX; e += 64) {
-      const int i = e / NX, j = e % NX;
-      double pij = sQxx[e], pji = sQxx[j * NX + i];
-      for (int u = 0; u < NU; ++u) {
-        pij += sQux[u * NX + i] * sK[u * NX + j];
-        pji += sQux[u * NX + j] * sK[u * NX + i];
+    {  // P = sym(Qxx + Qux^T K): both Qux^T K and its transpose K^T Qux in one K-step each
+      const double q0 = sQux[kq * NX + rc13], k0v = sK[kq * NX + rc13];
+      const double qk = r < NX ? q0 : 0.0, kk = r < NX ? k0v : 0.0;
+      const f64x4 zero = {};
+      const f64x4 dM = __builtin_amdgcn_mfma_f64_16x16x4f64(qk, kk, zero, 0, 0, 0);
+      const f64x4 dMT = __builtin_amdgcn_mfma_f64_16x16x4f64(kk, qk, zero, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = kq + 4 * v, j = r, ic = min(i, NX - 1);
+        const double xij = sQxx[ic * NX + rc13], xji = sQxx[rc13 * NX + ic];
+        if (i < NX && j < NX) {
+          const double pv = 0.5 * ((xij + dM[v]) + (xji + dMT[v]));
+          sP[i * NX + j] = pv;
+          if (a.P) a.P[(size_t)k * NX * NX + i * NX + j] = pv;
+        }
       }
-      const double v = 0.5 * (pij + pji);
-      sP[e] = v;
-      if (a.P) a.P[(size_t)k * NX * NX + e] = v;
     }
     if (t < NX) {
       double s = sqx[t];
       for (int u = 0; u < NU; ++u) s += sQux[u * NX + t] * skff[u];
       sp[t] = s;
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 

@@ -188,3 +188,22 @@ def test_box_lq_with_inactive_box_equals_unconstrained_step(torch):
     torch.cuda.synchronize()
     np.testing.assert_allclose(box["du"].cpu().numpy(), roll["du"].cpu().numpy(), atol=1e-9)
     np.testing.assert_allclose(box["dxN"].cpu().numpy(), roll["dxN"].cpu().numpy(), atol=1e-8)
+
+
+def test_prepared_call_matches_and_sees_new_data(torch):
+    """RiccatiCall marshals once; later calls use the current contents of A, B."""
+    import paper_2203_07747_amd as rtn
+    off = offsets_from_horizons(sample_horizons(7, 3, 20, seed=11))
+    n = int(off[-1])
+    Q, R = np.eye(13), 0.1 * np.eye(4)
+    A0, B0, _ = random_lq(n, 12)
+    At, Bt = torch.from_numpy(A0).cuda(), torch.from_numpy(B0).cuda()
+    call = rtn.RiccatiCall(At, Bt, Q, R, Q, offsets=off, want_P=True)
+    for seed in (13, 14):
+        A, B, _ = random_lq(n, seed)
+        At.copy_(torch.from_numpy(A))
+        Bt.copy_(torch.from_numpy(B))
+        print(f"[gpu] prepared riccati call, seed {seed}", flush=True)
+        got = {k: v.cpu().numpy() for k, v in call().items()}
+        K, kff, P = riccati_batched(off, A.astype(np.float64), B.astype(np.float64), Q, R, Q)
+        assert rel_max(got["K"], K) < 1e-9 and rel_max(got["P"], P) < 1e-9

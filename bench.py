@@ -308,7 +308,7 @@ def di_runtime(torch, rtn, stream, only=None):
         ms, wall = time_steps(torch, call, 400, 20, stream, warm_s=0.05)
         out = {}
         f = lambda: rtn.di_rti(x, u, xN, x0, m, Q, R, QN, dt, out=out, stream=stream)
-        ms_py, _ = time_steps(torch, f, 200, 20, stream)
+        ms_py, _ = time_steps(torch, f, 200, 20, stream, warm_s=0.05)
         if m is not None:
             m.close()
         return {"us_per_iteration": ms * 1e3, "hz": 1e3 / ms, "host_us_per_call": wall * 1e3,
@@ -319,8 +319,8 @@ def di_runtime(torch, rtn, stream, only=None):
         r = tick_time(L, H)
         r["weight_bytes"] = 4.0 * (3 * H + (L - 1) * (H * H + H) + 2 * H + 2)
         return {"nodes": N, "network": f"{L}x{H}", **r}
-    res = {"nodes": N, "loop": "back-to-back rtn_di_rti calls (prepared arguments, captured graph), "
-                               "timed with events on the stream",
+    res = {"nodes": N, "loop": "back-to-back rtn_di_rti calls (prepared arguments; one launch for widths "
+                               "<= 64, else a captured graph), timed with events on the stream",
            "nominal_only": tick_time(0, 0), "two_layer": {}, "table_ii": {}}
     for H in sorted(PAPER_RTX3000_HZ_TWO_LAYER):
         r = tick_time(2, H)

@@ -275,7 +275,7 @@ def linearize(x, u, model: Optional[Model] = None, prec: str = "fp32", dt: float
 
 class LinearizeCall:
     """rtn_linearize with its arguments checked and marshalled once: each call only
-    enqueues the linearisation (the library replays its captured graph), for
+    enqueues the linearisation (one launch, or the replay of a captured graph), for
     real-time loops that refill the same x, u tensors every tick."""
 
     def __init__(self, x, u, model: Optional[Model] = None, prec: str = "fp32", dt: float = 0.05, quad=None,
@@ -635,7 +635,7 @@ def di_rti(x, u, xN, x0, model: Optional[DiModel], Q, R, QN, dt: float = 0.05, o
 
 class DiRtiCall:
     """rtn_di_rti with its arguments checked and marshalled once: each call only
-    enqueues the iteration (the library replays its captured graph), for control
+    enqueues the iteration (one launch, or the replay of a captured graph), for control
     loops that refill the same input tensors every tick."""
 
     def __init__(self, x, u, xN, x0, model: Optional[DiModel], Q, R, QN, dt: float = 0.05, offsets=None,

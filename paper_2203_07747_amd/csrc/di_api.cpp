@@ -301,7 +301,9 @@ rtn_status rtn_di_rti(const rtn_di_model* model, float dt, int32_t n_inst, const
     ProfScope ps("di_rti", q);
     return launch_di_rti(n_inst, h->d_off, dt, cost, x, u, xN, x0, x_ref, y, J, du, dx, dxN, A, B, x_next, q);
   };
-  if (profiling_on()) {
+  // a single launch (the one-workgroup path, or the nominal model alone) gains
+  // nothing from a graph
+  if (profiling_on() || fused || !m) {
     DI_TRY(enqueue(st));
     return RTN_OK;
   }

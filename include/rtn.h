@@ -370,7 +370,8 @@ rtn_status rtn_di_linearize(const rtn_di_model* model, float dt, int32_t n_nodes
  * outputs (device fp64): du [n], dx [n][2] (dx_0..dx_{N-1}), dxN [n_inst][2];
  *   gaps c_k = x_next_k - x_{k+1} (x_N for the last node).  A [n][2][2],
  *   B [n][2], x_next [n][2] nullable (device fp32): the linearisation used.
- * Widths <= 64 (and a NULL model) run as one launch per call; wider networks, whose iteration is
+ * Widths <= 64 with at most 64 nodes per instance (and a NULL model) run as one
+ * launch per call; wider networks or longer horizons, whose iteration is
  * several launches, replay a HIP graph captured for each argument set. */
 rtn_status rtn_di_rti(const rtn_di_model* model, float dt, int32_t n_inst, const int32_t* offsets_host,
                       int32_t n_nodes, const double* Q_host, const double* R_host, const double* QN_host,

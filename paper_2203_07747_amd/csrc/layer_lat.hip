@@ -304,32 +304,21 @@ __device__ inline float fz_act(float a, int act, float* d) {
 }
 
 // acc[i] += A_i (16 x 64) B (64 x 16) on MFMA 16x16x4 fp32: lane (r, kq) supplies
-// A_i[r][k] = ap[i][k - kq] (times gp[i][k - kq] when gated) and B[k][c] =
-// bp[(k - kq) bk] for k = 4 st + kq; every operand is read from LDS before the
-// first product.
-template <int NT, bool GATE = false>
-__device__ inline void fz_k64(const float* const* ap, const float* bp, int bk, f32x4* acc,
-                              const float* const* gp = nullptr) {
+// A_i[r][k] = ap[i][k - kq] and B[k][c] = bp[(k - kq) bk] for k = 4 st + kq; every
+// operand is read from LDS before the first product.
+template <int NT>
+__device__ inline void fz_k64(const float* const* ap, const float* bp, int bk, f32x4* acc) {
   float a[NT][kFzH / 4], b[kFzH / 4];
 #pragma unroll
   for (int st = 0; st < kFzH / 4; ++st) {
     b[st] = bp[4 * st * bk];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) a[i][st] = GATE ? ap[i][4 * st] * gp[i][4 * st] : ap[i][4 * st];
+    for (int i = 0; i < NT; ++i) a[i][st] = ap[i][4 * st];
   }
 #pragma unroll
   for (int st = 0; st < kFzH / 4; ++st)
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][st], b[st], acc[i], 0, 0, 0);
-}
-
-template <int NT>
-__device__ inline void fz_k64_any(bool gate, const float* const* ap, const float* bp, int bk, f32x4* acc,
-                                  const float* const* gp) {
-  if (gate)
-    fz_k64<NT, true>(ap, bp, bk, acc, gp);
-  else
-    fz_k64<NT, false>(ap, bp, bk, acc);
 }
 
 __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n, const float* __restrict__ x,
@@ -421,46 +410,43 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
         fz_k64<1>(ap, wh + (l - 1) * kFzH * kFzS + c * kFzS + kq, 1, &acc);
       }
       float* zout = zf + (cur ^ 1) * kFzNodes * kFzS;
+      float wl[kDout];  // last layer: W_{L+1}[j][c], for the cotangent rows formed below
+#pragma unroll
+      for (int j = 0; j < kDout; ++j) wl[j] = wo[j * kFzH + c];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int q = 4 * kq + v;
         float dd;
         zout[q * kFzS + c] = fz_act(acc[v] + bs[l * kFzH + c], net.act, &dd);
         spd[l * kFzNodes * kFzS + q * kFzS + c] = dd;
+        if (l == L - 1)  // G_L[(q, j)][c] = W_{L+1}[j][c] act'(a_L)[q][c], into cotangent buffer 0
+#pragma unroll
+          for (int j = 0; j < kDout; ++j) gb[(q * kDout + j) * kFzS + c] = wl[j] * dd;
       }
     }
     __syncthreads();
     cur ^= 1;
   }
 
-  // reverse: G_{l-1} = (G_l W_l) (.) act'(a_{l-1}), where the first operand G_L =
-  // W_{L+1} (.) act'(a_L) (row (q, j) = W_{L+1}[j] (.) act'(a_L)[q]) is formed while
-  // loading; wave w owns column tile w % 4 and row tiles w / 4, w / 4 + 2, w / 4 + 4
-  // below nrt (W_l read once for all of them)
+  // reverse: G_{l-1} = (G_l W_l) (.) act'(a_{l-1}), from G_L (formed in the last
+  // forward epilogue); wave w owns column tile w % 4 and row tiles w / 4, w / 4 + 2,
+  // w / 4 + 4 below nrt (W_l read once for all of them)
   const int rows = nn * kDout, nrt = (rows + 15) / 16;
-  const float* spL = spd + (L - 1) * kFzNodes * kFzS;
   int gc = 0;
   for (int l = L - 1; l >= 1; --l) {
-    const bool first = l == L - 1;
     const float* gin = gb + gc * kFzRows * kFzS;
-    float* gout = gb + (first ? 0 : gc ^ 1) * kFzRows * kFzS;
+    float* gout = gb + (gc ^ 1) * kFzRows * kFzS;
     const int ct = wave & 3, rt0 = wave >> 2, c = ct * 16 + r, ntl = (nrt - rt0 + 1) / 2;  // uniform per wave
-    const float* ap[3];
-    const float* gp[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int p = (rt0 + 2 * i) * 16 + r, q = p / kDout;  // p < 96: q < 16
-      ap[i] = first ? wo + (p - q * kDout) * kFzH + kq : gin + p * kFzS + kq;
-      gp[i] = spL + q * kFzS + kq;
-    }
+    const float* ap[3] = {gin + (rt0 * 16 + r) * kFzS + kq, gin + ((rt0 + 2) * 16 + r) * kFzS + kq,
+                          gin + ((rt0 + 4) * 16 + r) * kFzS + kq};
     const float* bp = wh + (l - 1) * kFzH * kFzS + kq * kFzS + c;
     f32x4 acc[3] = {};
     if (ntl >= 3)
-      fz_k64_any<3>(first, ap, bp, kFzS, acc, gp);
+      fz_k64<3>(ap, bp, kFzS, acc);
     else if (ntl == 2)
-      fz_k64_any<2>(first, ap, bp, kFzS, acc, gp);
+      fz_k64<2>(ap, bp, kFzS, acc);
     else if (ntl == 1)
-      fz_k64_any<1>(first, ap, bp, kFzS, acc, gp);
+      fz_k64<1>(ap, bp, kFzS, acc);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       if (i >= ntl) continue;
@@ -471,18 +457,15 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
       }
     }
     __syncthreads();
-    gc = first ? 0 : gc ^ 1;
+    gc ^= 1;
   }
 
-  // J_D = G_1 W_1 ([rows][64] x [64][14]; G_1 = G_L formed on load when L = 1):
-  // wave w < nrt owns row tile w; wave 7 meanwhile forms y = W_{L+1} h_L + b_{L+1}
-  // (one 16 x 16 tile, 6 columns live)
+  // J_D = G_1 W_1 ([rows][64] x [64][14]): wave w < nrt owns row tile w; wave 7
+  // meanwhile forms y = W_{L+1} h_L + b_{L+1} (one 16 x 16 tile, 6 columns live)
   if (wave < nrt) {
-    const int p = wave * 16 + r, q = p / kDout;
-    const float* ap[1] = {L == 1 ? wo + (p - q * kDout) * kFzH + kq : gb + gc * kFzRows * kFzS + p * kFzS + kq};
-    const float* gp[1] = {spL + q * kFzS + kq};
+    const float* ap[1] = {gb + gc * kFzRows * kFzS + (wave * 16 + r) * kFzS + kq};
     f32x4 acc = {};
-    fz_k64_any<1>(L == 1, ap, w0 + kq * kFzW0S + r, kFzW0S, &acc, gp);  // columns r >= 14 are dropped
+    fz_k64<1>(ap, w0 + kq * kFzW0S + r, kFzW0S, &acc);  // columns r >= 14 are dropped
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int pv = wave * 16 + 4 * kq + v;

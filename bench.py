@@ -90,6 +90,8 @@ def parse():
     p.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-compare", action="store_true", help="skip the other-precision comparison runs")
+    p.add_argument("--no-fp8-workload", action="store_true",
+                   help="skip the fp8 configuration (65,536 instances x 20 nodes, 14-4x1024-6)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the latency, Riccati and training side measurements")
@@ -132,7 +134,64 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, gpu_K, seconds):
+def rel_rows(a, b):
+    """Per-node |a - b|_F / |b|_F."""
+    a = np.asarray(a, np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, np.float64).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-30)
+
+
+def stats(e):
+    return {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "median": float(np.median(e))}
+
+
+def errors_vs_oracle(gpu, gpu_nom, ref, ref_nom):
+    """Error of a GPU linearisation against the FP64 oracle on the same nodes: per-node
+    relative Frobenius error of x_{k+1}, A_k, B_k, J_D; of the network's share of the
+    continuity parameters (A - A_nominal, B - B_nominal, each side with its own nominal
+    step), which A and B hide behind their identity and nominal parts; and of f_D-bar
+    over the root-mean-square node norm of the oracle's f_D-bar."""
+    errs = {}
+    for name, r in zip(("x_next", "A", "B", "J_D"), (ref[0], ref[1], ref[2], ref[4])):
+        errs[name] = stats(rel_rows(gpu[name], r))
+    f = np.asarray(gpu["f_D"], np.float64)
+    scale = np.sqrt(np.mean(np.sum(ref[3] ** 2, axis=1)))
+    errs["f_D_over_rms"] = stats(np.linalg.norm(f - ref[3], axis=1) / scale)
+    for name, i in (("A_minus_A_nominal", 1), ("B_minus_B_nominal", 2)):
+        key = "A" if i == 1 else "B"
+        errs[name] = stats(rel_rows(np.asarray(gpu[key], np.float64) - gpu_nom[key], ref[i] - ref_nom[i]))
+    return errs
+
+
+def nominal_gpu(torch, rtn, x, u, dt):
+    out = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), None, "fp32", dt)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+def sample_outputs(torch, rtn, cfg, x, u, gpu_out, n_sample, seed):
+    """A seeded sample of the workload's nodes (first and last included): their inputs,
+    the GPU outputs and the GPU's nominal step of the same nodes."""
+    n = x.shape[0]
+    idx = np.unique(np.concatenate([np.random.default_rng(seed).choice(n, min(n, n_sample), replace=False),
+                                    [0, n - 1]]))
+    return {"cfg": cfg, "x": x[idx], "u": u[idx], "gpu": {k: v[idx] for k, v in gpu_out.items()},
+            "nom": nominal_gpu(torch, rtn, x[idx], u[idx], cfg.dt)}
+
+
+def sampled_errors(sample, Ws, bs):
+    """(CPU-baseline leg) errors_vs_oracle of a sample taken by sample_outputs."""
+    from oracle.mlp import MLP
+    from oracle.rk4 import linearize_affine
+    x, u, dt = sample["x"], sample["u"], sample["cfg"].dt
+    ref = linearize_affine(x, u, MLP(Ws, bs), dt)
+    ref_nom = linearize_affine(x, u, None, dt)
+    errs = errors_vs_oracle(sample["gpu"], sample["nom"], ref, ref_nom)
+    errs["sample_nodes"] = int(x.shape[0])
+    return errs
+
+
+def cpu_baseline(torch, rtn, cfg, off, x, u, Ws, bs, gpu_out, gpu_K, seconds):
     """The FP64 oracle, as it stands, on a bounded prefix of the same nodes (all host
     threads, then one thread); also the error of the GPU outputs on that prefix against
     it, and of the GPU's fp64 Riccati gains (on the GPU's A_k, B_k, and end to end)."""
@@ -141,7 +200,7 @@ def cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, gpu_K, seconds):
     from oracle.rk4 import linearize_affine
     from oracle.riccati import riccati_batched
     net = MLP(Ws, bs)
-    n_sample = min(2048, x.shape[0])
+    n_sample = min(8192, x.shape[0])
     done, t0 = 0, time.perf_counter()
     ref = None
     while True:
@@ -152,19 +211,17 @@ def cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, gpu_K, seconds):
             break
     elapsed = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
-    n1 = min(256, n_sample)
+    n1 = min(1024, n_sample)
     with threadpoolctl.threadpool_limits(1):
         done1, t1 = 0, time.perf_counter()
         while time.perf_counter() - t1 < seconds / 4:
             linearize_affine(x[:n1], u[:n1], net, cfg.dt)
             done1 += n1
         rate1 = done1 / (time.perf_counter() - t1)
-    errs = {}
-    for name, r in zip(("x_next", "A", "B", "f_D", "J_D"), ref):
-        g = gpu_out[name][:n_sample].reshape(n_sample, -1).astype(np.float64)
-        rr = r.reshape(n_sample, -1)
-        e = np.linalg.norm(g - rr, axis=1) / np.maximum(np.linalg.norm(rr, axis=1), 1e-30)
-        errs[name] = {"max": float(e.max()), "p999": float(np.quantile(e, 0.999))}
+    ref_nom = linearize_affine(x[:n_sample], u[:n_sample], None, cfg.dt)
+    errs = errors_vs_oracle({k: v[:n_sample] for k, v in gpu_out.items()},
+                            nominal_gpu(torch, rtn, x[:n_sample], u[:n_sample], cfg.dt), ref, ref_nom)
+    errs["sample_nodes"] = n_sample
     # Riccati gains (Q = I, R = 0.1 I, Q_N = Q) of the instances inside the prefix
     n_inst = int(np.searchsorted(off, n_sample, side="right")) - 1
     o = off[:n_inst + 1]
@@ -174,14 +231,13 @@ def cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, gpu_K, seconds):
                                    Q, R, Q)
     K_ref, _, _ = riccati_batched(o, ref[1][:m], ref[2][:m], Q, R, Q)
     for name, Kr in (("K_same_AB", K_same), ("K_end_to_end", K_ref)):
-        g = gpu_K[:m].reshape(m, -1)
-        rr = Kr.reshape(m, -1)
-        e = np.linalg.norm(g - rr, axis=1) / np.maximum(np.linalg.norm(rr, axis=1), 1e-30)
-        errs[name] = {"max": float(e.max()), "p999": float(np.quantile(e, 0.999)), "instances": n_inst}
+        e = rel_rows(gpu_K[:m], Kr)
+        errs[name] = {**stats(e), "instances": n_inst}
     cpu = {"value": done / elapsed, "unit": "nodes/s", "cores": int(threads), "kind": "oracle",
            "sample": f"first {n_sample} nodes of the workload, fp64 NumPy oracle, repeated for "
                      f"{elapsed:.1f} s ({done} node linearisations)",
-           "single_thread_value": rate1, "cpu_model": cpu_model()}
+           "single_thread_value": rate1, "single_thread_sample": f"first {n1} nodes",
+           "cpu_model": cpu_model()}
     return cpu, errs
 
 
@@ -334,6 +390,83 @@ def di_runtime(torch, rtn, stream, only=None):
     return res
 
 
+def measure(torch, rtn, model, key, prec, xt, ut, off, cfg, steps, warmup, stream, out):
+    """Time `steps` rtn_linearize calls of one workload at one precision (the first call
+    tunes the tiles), then collect per-kernel event times over as many calls."""
+    n = xt.shape[0]
+    L, H = cfg.n_hidden, cfg.width
+
+    def step():
+        rtn.linearize(xt, ut, model, prec, cfg.dt, offsets=off, out=out, stream=stream)
+
+    ms, wall_ms = time_steps(torch, step, steps, warmup, stream)
+    rtn.profile_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    kern = rtn.profile_collect()
+    rtn.profile_enable(False)
+    f_fwd, f_rev = flops_per_node(L, H)
+    nan = {"avg_ms": float("nan"), "total_ms": float("nan"), "calls": 0}
+    krev = kern.get("mlp_reverse_chain", nan)
+    launches = max(1, round(krev["calls"] / steps))
+    # algorithmic flops of all reverse launches over their summed event durations
+    achieved = n * f_rev * steps / (krev["total_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    return {
+        "value": n / (ms * 1e-3), "ms_per_step": ms, "steps": steps, "host_wall_ms_per_step": wall_ms,
+        "roofline": {"bound": "mfma", "kernel": "mlp_reverse_chain", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(key, "mlp_reverse_chain", n // launches),
+                     "algorithmic_flops_per_launch": n * f_rev / launches, "avg_launch_ms": krev["avg_ms"],
+                     "launches_per_step": launches},
+        "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
+        "tile_choice": tile_choice(rtn, prec, H, L, n // launches),
+        "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,
+    }
+
+
+def workload(torch, rtn, key, steps, warmup, stream, compare, fixed_fp32=False):
+    """One configuration at its own precision and (compare) at the other two; returns the
+    measurement record and what the side measurements need."""
+    cfg, off, x, u, Ws, bs = config_workload(key)
+    n = x.shape[0]
+    model = rtn.Model(Ws, bs)
+    xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
+    calibrated = False
+
+    def ensure_calibrated():
+        nonlocal calibrated
+        if not calibrated:
+            xc, uc = sample_nodes(65536, seed=SEED_CALIB)
+            model.calibrate(torch.from_numpy(xc).cuda(), torch.from_numpy(uc).cuda())
+            calibrated = True
+
+    prec = cfg.precision
+    if prec == "fp8":
+        ensure_calibrated()
+    out = {}
+    rec = measure(torch, rtn, model, key, prec, xt, ut, off, cfg, steps, warmup, stream, out)
+    rec["config"] = {"workload": cfg.name, "n_inst": int(len(off) - 1), "n_nodes": int(n),
+                     "hidden_layers": cfg.n_hidden, "width": cfg.width, "dt": cfg.dt}
+    rec["dtype"] = prec
+    gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
+    if compare:
+        cmp = {}
+        for p in ("fp32", "bf16", "fp8"):
+            if p == prec:
+                continue
+            if p == "fp8":
+                ensure_calibrated()
+            if p == "fp32" and fixed_fp32:  # default shapes, no tuning sweep at this size
+                rtn.tune_set("fp32", cfg.width, cfg.n_hidden, n, (0, 0, 0, 0, 0))
+            cmp[p] = measure(torch, rtn, model, key, p, xt, ut, off, cfg, max(3, steps // 5), 2, stream, {})
+            if fixed_fp32 and p == "fp32":
+                cmp[p]["tile_choice"]["note"] = "default shapes, not tuned"
+        rec["other_precisions_same_workload"] = cmp
+    return rec, (cfg, off, x, u, Ws, bs, model, out, gpu_out)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -354,91 +487,47 @@ def main():
     import paper_2203_07747_amd as rtn
 
     torch.cuda.set_device(0)
-    cfg, off, x, u, Ws, bs = config_workload(args.config)
-    n = x.shape[0]
-    prec = cfg.precision
-    L, H = cfg.n_hidden, cfg.width
-    model = rtn.Model(Ws, bs)
-    xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
-    calibrated = False
-
-    def ensure_calibrated():
-        nonlocal calibrated
-        if not calibrated:
-            xc, uc = sample_nodes(65536, seed=SEED_CALIB)
-            model.calibrate(torch.from_numpy(xc).cuda(), torch.from_numpy(uc).cuda())
-            calibrated = True
-
-    if prec == "fp8":
-        ensure_calibrated()
     stream = torch.cuda.current_stream()
-    out = {}
-
-    def step(p=prec):
-        rtn.linearize(xt, ut, model, p, cfg.dt, offsets=off, out=out, stream=stream)
-
-    ms, wall_ms = time_steps(torch, step, args.steps, args.warmup, stream)
-    value = n / (ms * 1e-3)
-
-    # per-kernel durations from events bracketing each kernel on the launching stream
-    rtn.profile_enable(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    kern = rtn.profile_collect()
-    rtn.profile_enable(False)
-    gpu_out = {k: v.cpu().numpy() for k, v in out.items()}
-
-    f_fwd, f_rev = flops_per_node(L, H)
-    nan = {"avg_ms": float("nan"), "total_ms": float("nan"), "calls": 0}
-    krev = kern.get("mlp_reverse_chain", nan)
-    rev_ms = krev["avg_ms"]
-    fwd_ms = kern.get("mlp_forward_chain", nan)["avg_ms"]
-    rk4_ms = kern.get("rk4_linearize", nan)["avg_ms"]
-    launches = max(1, round(krev["calls"] / args.steps))  # large batches run as node chunks
-    # algorithmic flops of all reverse launches over their summed event durations
-    achieved = n * f_rev * args.steps / (krev["total_ms"] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[prec]
+    rec, (cfg, off, x, u, Ws, bs, model, out, gpu_out) = workload(torch, rtn, args.config, args.steps, args.warmup,
+                                                                   stream, not args.no_compare)
+    print(f"{args.config}: {rec['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     result = {
-        "metric": METRIC, "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": cfg.name, "n_inst": int(len(off) - 1), "n_nodes": int(n),
-                   "hidden_layers": L, "width": H, "dt": cfg.dt},
-        "roofline": {"bound": "mfma", "kernel": "mlp_reverse_chain", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(args.config, "mlp_reverse_chain", n // launches),
-                     "algorithmic_flops_per_launch": n * f_rev / launches, "avg_launch_ms": rev_ms,
-                     "launches_per_step": launches},
-        "kernels_ms": {"mlp_forward_chain": fwd_ms, "mlp_reverse_chain": rev_ms, "rk4_linearize": rk4_ms},
-        "tile_choice": tile_choice(rtn, prec, H, L, n // launches),
-        "whole_step_mfma_frac": n * (f_fwd + f_rev) / (ms * 1e-3) / 1e12 / peak,
-        "host_wall_ms_per_step": wall_ms,
+        "metric": METRIC, "value": rec["value"], "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": rec["dtype"], "data": "synthetic", "config": rec["config"],
+        "roofline": rec["roofline"],
     }
-    if not args.no_compare:
-        cmp = {}
-        for p in ("fp32", "bf16", "fp8"):
-            if p == prec:
-                continue
-            if p == "fp8":
-                ensure_calibrated()
-            o2 = {}
-            def s2(pp=p, oo=o2):
-                rtn.linearize(xt, ut, model, pp, cfg.dt, offsets=off, out=oo, stream=stream)
-            k2 = max(3, args.steps // 5)
-            m2, _ = time_steps(torch, s2, k2, 2, stream)
-            cmp[p] = {"value": n / (m2 * 1e-3), "ms_per_step": m2, "steps": k2,
-                      "mfma_frac": n * (f_fwd + f_rev) / (m2 * 1e-3) / 1e12 / PEAK_TFLOPS[p]}
-        result["other_precisions_same_workload"] = cmp
+    for k in ("kernels_ms", "tile_choice", "whole_step_mfma_frac", "host_wall_ms_per_step",
+              "other_precisions_same_workload"):
+        if k in rec:
+            result[k] = rec[k]
+    sample3 = sample_outputs(torch, rtn, cfg, x, u, gpu_out, 1500, 11) if not args.no_cpu else None
+    sample8 = None
+    if args.config != "c4" and not args.no_fp8_workload:
+        # the fp8 configuration of the metric: 65,536 instances x 20 nodes, 14-4x1024-6 e4m3
+        r8, (cfg8, _, x8, u8, Ws8, bs8, m8, out8, gpu8) = workload(
+            torch, rtn, "c4", max(5, args.steps // 4), 3, stream, not args.no_compare, fixed_fp32=True)
+        print(f"c4: {r8['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        if not args.no_cpu:
+            sample8 = sample_outputs(torch, rtn, cfg8, x8, u8, gpu8, 256, 12)
+        result["fp8_workload"] = r8
+        m8.close()
+        del out8, gpu8
+        torch.cuda.empty_cache()
     if not args.no_extras:
         result["extras"] = extras(torch, rtn, out, off, stream)
         result["extras"]["double_integrator_rti"] = di_runtime(torch, rtn, stream)
-    if not args.no_cpu:
+    if not args.no_cpu:  # the CPU-baseline leg: the FP64 oracle timed, and the GPU's errors against it
         ric = rtn.riccati(out["A"], out["B"], np.eye(13), 0.1 * np.eye(4), np.eye(13), offsets=off, stream=stream)
         torch.cuda.synchronize()
-        cpu, errs = cpu_baseline(cfg, off, x, u, Ws, bs, gpu_out, ric["K"].cpu().numpy(), args.cpu_seconds)
+        cpu, errs = cpu_baseline(torch, rtn, cfg, off, x, u, Ws, bs, gpu_out, ric["K"].cpu().numpy(),
+                                 args.cpu_seconds)
         result["cpu_baseline"] = cpu
         result["err_vs_fp64"] = errs
+        result["err_vs_fp64_sampled"] = sampled_errors(sample3, Ws, bs)
+        if sample8 is not None:
+            result["fp8_workload"]["err_vs_fp64_sampled"] = sampled_errors(sample8, Ws8, bs8)
+    model.close()
     print(json.dumps(result), flush=True)
 
 

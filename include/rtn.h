@@ -120,15 +120,22 @@ rtn_status rtn_model_create(const rtn_mlp_desc* desc, const float* params_host, 
 rtn_status rtn_model_destroy(rtn_model* model);
 
 /* Replace / read back the fp32 master parameters (host buffers, layout as
- * rtn_param_count).  Synchronous.  Setting parameters resets nothing else. */
+ * rtn_param_count).  Synchronous.  Setting parameters keeps the gradients and
+ * Adam state and clears the fp8 calibration (its activation and cotangent
+ * scales were measured on the old weights): RTN_FP8 calls fail with RTN_EINVAL
+ * until rtn_model_calibrate runs again. */
 rtn_status rtn_model_set_params(rtn_model* model, const float* params_host);
 rtn_status rtn_model_get_params(rtn_model* model, float* params_host);
 
-/* Static FP8 scales.  Weight scales are amax(|W_l|)/448 and are refreshed
- * whenever parameters change.  Activation and cotangent scales are measured by
- * running the network and its reverse sweep in fp32 over n calibration nodes
- * (device x [n][13], u [n][4]) and taking amax/448 per tensor.  Synchronous.
- * RTN_FP8 calls on an uncalibrated model fail with RTN_EINVAL. */
+/* Static FP8 scales (the paper states no precision; the format and the scale
+ * rule amax/448 are this library's choice).  Weight scales are amax(|W_l|)/448
+ * and are refreshed whenever parameters change.  Activation and cotangent
+ * scales are measured by running the network and its reverse sweep in fp32 over
+ * n calibration nodes (device x [n][13], u [n][4]) and taking amax/448 per
+ * tensor.  Synchronous.  RTN_FP8 calls on an uncalibrated model fail with
+ * RTN_EINVAL, and every change of the parameters (rtn_model_set_params, an Adam
+ * update of rtn_train_step or rtn_adam_step) returns the model to uncalibrated.
+ * Finite operands beyond +-448 times their scale saturate; NaN stays NaN. */
 rtn_status rtn_model_calibrate(rtn_model* model, int32_t n, const float* x, const float* u, void* stream);
 
 /* Copy the scales to host: scales[0 .. 3L+2) = { weight scale of W_1..W_{L+1},
@@ -256,13 +263,18 @@ rtn_status rtn_lq_rollout(int32_t n_inst, const int32_t* offsets_host, int32_t n
                           double* dx, double* du, double* dxN, void* stream);
 
 /* Network forward pass over a batch (device in [batch][14] -> out [batch][6]),
- * stashing what rtn_mlp_backward needs in the model.  prec RTN_FP32 or RTN_BF16. */
+ * stashing what rtn_mlp_backward needs in the model: the residual network of
+ * eq. (7) evaluated on training inputs (Sec. VII fits it offline to the
+ * simulator's residual accelerations).  prec RTN_FP32 or RTN_BF16; the paper
+ * states no precision, bf16 products with fp32 accumulation and fp32 master
+ * weights are this library's choice. */
 rtn_status rtn_mlp_forward(rtn_model* model, int32_t prec, int32_t batch,
                            const float* in, float* out, void* stream);
 
 /* Backward pass of the last rtn_mlp_forward (same batch): given dL/dout
  * (device [batch][6]), ADD dL/dparams into the model's gradient buffer and, if
- * din is not NULL, write dL/din (device [batch][14]). */
+ * din is not NULL, write dL/din (device [batch][14]).  Exact backpropagation
+ * through the network of eq. (7), in the precision of that forward pass. */
 rtn_status rtn_mlp_backward(rtn_model* model, int32_t batch, const float* dout, float* din,
                             void* stream);
 

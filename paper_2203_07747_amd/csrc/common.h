@@ -115,10 +115,12 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
 }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// Two floats -> two OCP E4M3 bytes (saturated to +-448, round to nearest even).
+// Two floats -> two OCP E4M3 bytes (finite values saturated to +-448, round to
+// nearest even; a NaN stays NaN, so a poisoned operand still reaches the status check).
+__device__ inline float sat448(float a) { return a != a ? a : fminf(fmaxf(a, -448.f), 448.f); }
 __device__ inline uint32_t f32x2_to_e4m3(float a, float b) {
-  a = fminf(fmaxf(a, -448.f), 448.f);
-  b = fminf(fmaxf(b, -448.f), 448.f);
+  a = sat448(a);
+  b = sat448(b);
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
 }
 

@@ -376,6 +376,7 @@ rtn_status rtn_model_set_params(rtn_model* model, const float* params_host) {
   HIP_TRY(hipDeviceSynchronize());
   const std::vector<float> full = m->expand(params_host);
   HIP_TRY(hipMemcpy(m->params, full.data(), m->n_params * 4, hipMemcpyHostToDevice));
+  m->calibrated = false;  // activation and cotangent scales belong to the old weights
   rtn_status s = m->repack(nullptr);
   if (s) return s;
   HIP_TRY(hipStreamSynchronize(nullptr));
@@ -966,6 +967,7 @@ static rtn_status adam_update(Model* m, float lr, float b1, float b2, float eps,
     HIP_TRY(launch_adam(m->n_params, m->params, m->grad, m->adam_m, m->adam_v, lr, b1, b2, eps, bc1, bc2, st));
   }
   m->invalidate_packs();  // packed copies are refreshed by the next call that needs one
+  m->calibrated = false;  // fp8 activation and cotangent scales belong to the old weights
   return RTN_OK;
 }
 

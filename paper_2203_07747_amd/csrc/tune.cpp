@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 namespace rtn {
@@ -170,27 +171,34 @@ hipError_t tune_run(int prec, int H, const NetView& net, int n, const float* x, 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
-  // average time of `reps` launches after one untimed launch
+  // Time of one candidate: one untimed launch, then three timed rounds of `reps`
+  // back-to-back launches (reps from a first timed launch: more for short kernels);
+  // the median round's average is kept, so one disturbed round (a clock change, a
+  // neighbour on the device) cannot make a slow candidate look fast or a fast one slow.
   auto time_launch = [&](auto&& launch, float* ms) -> hipError_t {
     hipError_t e = launch();
     if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
-    if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-    float t = 0.f;
-    if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
-    int reps = t > 20.f ? 1 : (t > 2.f ? 3 : 8);
-    if (reps > 1) {
-      if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+    auto round = [&](int reps, float* t) -> hipError_t {
+      hipError_t r;
+      if ((r = hipEventRecord(e0, st)) != hipSuccess) return r;
       for (int i = 0; i < reps; ++i)
-        if ((e = launch()) != hipSuccess) return e;
-      if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-      if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
-      t /= (float)reps;
-    }
-    *ms = t;
+        if ((r = launch()) != hipSuccess) return r;
+      if ((r = hipEventRecord(e1, st)) != hipSuccess) return r;
+      if ((r = hipEventSynchronize(e1)) != hipSuccess) return r;
+      if ((r = hipEventElapsedTime(t, e0, e1)) != hipSuccess) return r;
+      *t /= (float)reps;
+      return hipSuccess;
+    };
+    float t0 = 0.f;
+    if ((e = round(1, &t0)) != hipSuccess) return e;
+    const int reps = t0 > 20.f ? 1 : (t0 > 2.f ? 2 : 6);
+    float t[3];
+    for (int k = 0; k < 3; ++k)
+      if ((e = round(reps, &t[k])) != hipSuccess) return e;
+    if (t[0] > t[1]) std::swap(t[0], t[1]);
+    if (t[1] > t[2]) std::swap(t[1], t[2]);
+    if (t[0] > t[1]) std::swap(t[0], t[1]);
+    *ms = t[1];
     return hipSuccess;
   };
   TuneChoice best;

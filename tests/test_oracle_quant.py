@@ -215,3 +215,27 @@ def test_accumulation_order_spread(key, fmt, n, n_calib):
     assert np.median(ry) < b["median"] / 10 and np.median(rJ) < b["median"] / 10
     assert max(ry.max(), rJ.max()) > 1e3 * max(np.median(ry), np.median(rJ))  # flips exist
     assert max(ry.max(), rJ.max()) < b["max"] / 2
+
+
+def test_fp8_accumulation_model_sizes_the_emulation_bounds():
+    """The fp8 emulation bounds come from the emulation with every product output
+    perturbed at the fp8 matrix cores' measured accumulation level (relative 3e-5):
+    on the 14-4x1024-6 network that level flips enough later E4M3 roundings to move
+    the typical node by ~1e-2, while a perturbation at fp32 level (1e-7) barely moves
+    it; the bounds derived from it stay below what a zeroed or halved J_D gives."""
+    from net_bounds import FP8_ACCUMULATION_EPS, fp8_emulation_bounds, perturbed_fp8_emulation
+    cfg, off, x, u, Ws, bs = config_workload("c4")
+    net = MLP(Ws, bs)
+    xc, uc = sample_nodes(2048, seed=SEED_CALIB)
+    sc = calibrate_scales(net, pack_input(xc, uc))
+    z = pack_input(*sample_nodes(100, seed=1))
+    ye, Je = emulated_jacobian(net, z, "fp8", sc)
+    yp, Jp = perturbed_fp8_emulation(net, z, sc, eps=1e-7)
+    assert np.median(rel_rows(Jp, Je)) < 1e-5 and np.median(rms_rows(yp, ye)) < 1e-5
+    yp, Jp = perturbed_fp8_emulation(net, z, sc, eps=FP8_ACCUMULATION_EPS)
+    med = np.median(rel_rows(Jp, Je))
+    print(f"perturbed at {FP8_ACCUMULATION_EPS}: median J_D {med:.2e}")
+    assert 1e-3 < med < 0.1
+    b = fp8_emulation_bounds(net, z, sc, ye, Je)
+    assert b["max"] <= 0.45 and b["median"] < 0.25
+    assert np.median(rel_rows(0.5 * Je, Je)) > b["median"] and rel_rows(0.0 * Je, Je).max() > b["max"]

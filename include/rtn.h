@@ -221,6 +221,22 @@ rtn_status rtn_riccati(int32_t n_inst, const int32_t* offsets_host, int32_t n_no
                        const double* q, const double* r, const double* qN,
                        double* K, double* kff, double* P, void* stream);
 
+/* rtn_riccati without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, outputs and results are those of rtn_riccati; the
+ * cost matrices and instance offsets are staged in a fixed library-owned device
+ * array (one per device, held until the process ends; about 260 KB) instead of
+ * a stream-ordered allocation, so at most 65536 instances per call
+ * (RTN_EINVAL beyond, nothing enqueued).  Calls that overlap on one device
+ * (two host threads, or two streams running concurrently) race on that array;
+ * calls on one stream are ordered.  The host arrays are consumed before the call
+ * returns. */
+rtn_status rtn_riccati_noalloc(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
+                               const float* A, const float* B, const double* c,
+                               const double* Q_host, const double* R_host, const double* QN_host,
+                               const double* q, const double* r, const double* qN,
+                               double* K, double* kff, double* P, void* stream);
+
 /* The same LQ problem with the input box of the QP (the input rows of eq. (3),
  * e.g. 0 <= u <= u_max written as du_lo = -u_k, du_hi = u_max - u_k):
  *   du_lo[k] <= du_k <= du_hi[k]  elementwise,

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ACT, INPUT, MlpDesc, Quad, check, load
 
-__all__ = ["Model", "DiModel", "DiRtiCall", "LinearizeCall", "RiccatiCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
+__all__ = ["Model", "DiModel", "DiRtiCall", "LinearizeCall", "RiccatiCall", "di_linearize", "di_rti", "linearize", "linearize_exact", "linearize_second", "riccati", "riccati_noalloc", "riccati_box", "lq_rollout", "version", "quad_struct", "PREC",
            "profile_enable", "profile_collect", "tune_mode", "tune_get", "tune_set", "tune_save", "tune_load"]
 
 
@@ -367,7 +367,7 @@ def linearize_second(x, u, model: Model, dt: float = 0.05, quad=None, offsets: O
 
 
 def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_P: bool = False,
-            out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
+            out: Optional[Dict[str, object]] = None, stream=None, _entry: str = "rtn_riccati") -> Dict[str, object]:
     """rtn_riccati over device tensors A [n,13,13], B [n,13,4] (fp32); Q, R, QN host arrays (fp64).
 
     Returns K [n,4,13], kff [n,4] and optionally P [n,13,13] (fp64 device tensors)."""
@@ -393,7 +393,7 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
     Rh = np.ascontiguousarray(R, dtype=np.float64)
     QNh = np.ascontiguousarray(QN, dtype=np.float64)
     f64 = torch.float64
-    check(load().rtn_riccati(n_inst, off_ptr, n, _dev(A, torch.float32, (n, 13, 13), "A"),
+    check(getattr(load(), _entry)(n_inst, off_ptr, n, _dev(A, torch.float32, (n, 13, 13), "A"),
                              _dev(B, torch.float32, (n, 13, 4), "B"),
                              _dev(c, f64, (n, 13), "c") if c is not None else None,
                              Qh.ctypes.data_as(ctypes.c_void_p), Rh.ctypes.data_as(ctypes.c_void_p),
@@ -403,8 +403,15 @@ def riccati(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_
                              _dev(qN, f64, (n_inst, 13), "qN") if qN is not None else None,
                              _dev(K, f64, (n, 4, 13), "K"), _dev(kff, f64, (n, 4), "kff"),
                              _dev(P, f64, (n, 13, 13), "P") if P is not None else None,
-                             _stream(stream)), "rtn_riccati")
+                             _stream(stream)), _entry)
     return out
+
+
+def riccati_noalloc(A, B, Q, R, QN, offsets=None, c=None, q=None, r=None, qN=None, want_P: bool = False,
+                    out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
+    """rtn_riccati_noalloc: rtn_riccati without any device allocation in the library
+    (at most 65536 instances).  Pass `out` with K, kff (and P) to allocate nothing here either."""
+    return riccati(A, B, Q, R, QN, offsets, c, q, r, qN, want_P, out, stream, _entry="rtn_riccati_noalloc")
 
 
 class RiccatiCall:

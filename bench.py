@@ -310,12 +310,17 @@ def extras(torch, rtn, lin_out, off, stream):
     uk = torch.full((n_all, 4), 9.81 / 4, device="cuda", dtype=torch.float64)
     lo, hi = (-uk).contiguous(), (4.0 - uk).contiguous()
     bout = {}
+    max_iter, tol = 400, 1e-6
     f = lambda: rtn.riccati_box(lin_out["A"], lin_out["B"], Q, R, Q, dx0, lo, hi, offsets=off, rho=1.0,
-                                max_iter=200, tol=1e-6, out=bout, stream=stream)
+                                max_iter=max_iter, tol=tol, out=bout, stream=stream)
     ms, _ = time_steps(torch, f, 5, 1, stream)
     it = bout["iters"].cpu().numpy()
-    res["riccati_box_fp64"] = {"ms_per_call": ms, "instances": int(len(off) - 1),
-                               "iterations_max": int(it.max()), "iterations_median": float(np.median(it))}
+    rs = bout["resid"].cpu().numpy()
+    unconv = (it >= max_iter) & (rs.max(axis=1) >= tol)
+    res["riccati_box_fp64"] = {"ms_per_call": ms, "instances": int(len(off) - 1), "tol": tol, "max_iter": max_iter,
+                               "iterations_max": int(it.max()), "iterations_median": float(np.median(it)),
+                               "unconverged_instances": int(unconv.sum()),
+                               "residual_max_primal": float(rs[:, 0].max()), "residual_max_dual": float(rs[:, 1].max())}
     Ws, bs = xp(TRAIN["n_hidden"], TRAIN["width"], seed=0)
     m = rtn.Model(Ws, bs)
     B = TRAIN["batch"]

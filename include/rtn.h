@@ -242,24 +242,28 @@ rtn_status rtn_riccati_noalloc(int32_t n_inst, const int32_t* offsets_host, int3
  *   du_lo[k] <= du_k <= du_hi[k]  elementwise,
  * solved per instance by ADMM on the split du = z (z in the box): the Riccati
  * recursion of R + rho I is computed once, then each iteration is one backward
- * pass of the linear terms, one rollout from dx_0, a projection onto the box and
- * a dual update, until max |du - z| < tol and rho max |z - z_prev| < tol, or
- * max_iter iterations.  Same A, B, c, Q, R, Q_N, q, r, qN as rtn_riccati, plus
+ * pass of the linear terms, one rollout from dx_0, an over-relaxed (1.6)
+ * projection onto the box and a dual update, until max |du - z| < tol and
+ * rho max |z - z_prev| < tol, or max_iter iterations.  Same A, B, c, Q, R, Q_N,
+ * q, r, qN as rtn_riccati, plus
  *   dx0           device fp64 [n_inst][13]: initial deviation of each instance
  *   du_lo, du_hi  device fp64 [n][4] (du_lo <= du_hi required; the projection is
  *                 min(max(v, lo), hi))
  *   rho > 0, max_iter >= 1, tol > 0
  * outputs (device): du fp64 [n][4] (inside the box); dx nullable fp64 [n][13] and
  * dxN nullable fp64 [n_inst][13] rolled out with du; iters nullable int32
- * [n_inst]: iterations used (max_iter when not converged).  Scratch memory is
- * allocated and freed stream-ordered.  Errors as rtn_riccati. */
+ * [n_inst]: iterations used (max_iter when not converged); resid nullable fp64
+ * [n_inst][2]: primal and dual residual of the last iteration (an instance with
+ * iters == max_iter and a residual above tol did not converge).  Scratch memory
+ * is allocated and freed stream-ordered.  Errors as rtn_riccati. */
 rtn_status rtn_riccati_box(int32_t n_inst, const int32_t* offsets_host, int32_t n_nodes,
                            const float* A, const float* B, const double* c,
                            const double* Q_host, const double* R_host, const double* QN_host,
                            const double* q, const double* r, const double* qN,
                            const double* dx0, const double* du_lo, const double* du_hi,
                            double rho, int32_t max_iter, double tol,
-                           double* du, double* dx, double* dxN, int32_t* iters, void* stream);
+                           double* du, double* dx, double* dxN, int32_t* iters, double* resid,
+                           void* stream);
 
 /* Forward pass of the LQ solution returned by rtn_riccati: the primal step of
  * the QP of Sec. IV-A (the step the feedback phase applies, Sec. IV-B).  Per

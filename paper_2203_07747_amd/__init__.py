@@ -445,7 +445,8 @@ def riccati_box(A, B, Q, R, QN, dx0, du_lo, du_hi, offsets=None, c=None, q=None,
                 rho: float = 1.0, max_iter: int = 500, tol: float = 1e-8, want_dx: bool = True,
                 out: Optional[Dict[str, object]] = None, stream=None) -> Dict[str, object]:
     """rtn_riccati_box: the LQ step with the input box du_lo <= du <= du_hi (ADMM).
-    Returns du [n,4], iters [n_inst] (int32) and optionally dx [n,13], dxN [n_inst,13]."""
+    Returns du [n,4], iters [n_inst] (int32), resid [n_inst,2] (primal, dual residual of
+    the last iteration) and optionally dx [n,13], dxN [n_inst,13]."""
     torch = _torch()
     n = A.shape[0]
     dev = A.device
@@ -464,6 +465,7 @@ def riccati_box(A, B, Q, R, QN, dx0, du_lo, du_hi, offsets=None, c=None, q=None,
     f64 = torch.float64
     du = get("du", (n, 4))
     iters = get("iters", (n_inst,), torch.int32)
+    resid = get("resid", (n_inst, 2))
     dx = get("dx", (n, 13)) if want_dx else None
     dxN = get("dxN", (n_inst, 13)) if want_dx else None
     Qh = np.ascontiguousarray(Q, dtype=np.float64)
@@ -482,7 +484,8 @@ def riccati_box(A, B, Q, R, QN, dx0, du_lo, du_hi, offsets=None, c=None, q=None,
                                  _dev(du, f64, (n, 4), "du"),
                                  _dev(dx, f64, (n, 13), "dx") if dx is not None else None,
                                  _dev(dxN, f64, (n_inst, 13), "dxN") if dxN is not None else None,
-                                 _dev(iters, torch.int32, (n_inst,), "iters"), _stream(stream)), "rtn_riccati_box")
+                                 _dev(iters, torch.int32, (n_inst,), "iters"), _dev(resid, f64, (n_inst, 2), "resid"),
+                                 _stream(stream)), "rtn_riccati_box")
     return out
 
 

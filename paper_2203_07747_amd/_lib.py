@@ -61,7 +61,7 @@ SIGNATURES = {
     "rtn_riccati_box": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   ctypes.c_double, c_int32, ctypes.c_double, c_void_p, c_void_p, c_void_p,
-                                  c_void_p, c_void_p]),
+                                  c_void_p, c_void_p, c_void_p]),
     "rtn_lq_rollout": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rtn_di_param_count": (c_int32, [c_int32, c_int32, P(c_int64)]),

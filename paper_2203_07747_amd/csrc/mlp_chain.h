@@ -129,7 +129,7 @@ hipError_t launch_box_admm(int n_inst, const int* offsets, const float* A, const
                            const double* QN, const double* Rt, const double* q, const double* r, const double* qN,
                            const double* K, const double* P, const double* dx0, const double* lo, const double* hi,
                            double rho, double tol, int max_iter, double* ws, double* du, double* dx, double* dxN,
-                           int* iters, hipStream_t st);
+                           int* iters, double* resid, hipStream_t st);
 hipError_t launch_riccati(int n_inst, const int* offsets, const double* Q, const double* R, const double* QN,
                           const float* A, const float* B, const double* c, const double* q, const double* r,
                           const double* qN, double* K, double* kff, double* P, hipStream_t st);

@@ -282,9 +282,14 @@ hipError_t launch_lq_rollout(int n_inst, const int* offsets, const float* A, con
 //            recursion (K_k, P_k) does not change between iterations, so it is
 //            computed once (riccati_kernel) and each iteration is one backward pass
 //            of the vectors and one rollout;
-//   z-step : z_k = clip(du_k + y_k, lo_k, hi_k);   y-step: y_k += du_k - z_k.
-// Stops when max |du - z| and rho max |z - z_prev| are both below tol.  The
-// returned inputs are z (inside the box) and the states rolled out with them.
+//   z-step : z_k = clip(a du_k + (1 - a) z_k + y_k, lo_k, hi_k);
+//   y-step : y_k += a du_k + (1 - a) z_k_prev - z_k,
+// with the over-relaxation a = 1.6 of Boyd et al. (Distributed optimization and
+// statistical learning via ADMM, Sec. 3.4.3), which fixes the same minimiser and
+// takes fewer iterations than a = 1.  Stops when max |du - z| and
+// rho max |z - z_prev| are both below tol.  The returned inputs are z (inside the
+// box) and the states rolled out with them; resid reports both measures of the
+// last iteration.
 struct BoxArgs {
   const int* offsets;
   const float* A;
@@ -307,7 +312,10 @@ struct BoxArgs {
   double* dx;        // nullable [n][13]
   double* dxN;       // nullable [n_inst][13]
   int* iters;        // nullable [n_inst]
+  double* resid;     // nullable [n_inst][2]: primal, dual residual of the last iteration
 };
+
+constexpr double kBoxRelax = 1.6;
 
 constexpr int kBoxWs = kBoxWsDoubles;
 
@@ -424,10 +432,11 @@ __global__ void __launch_bounds__(64) box_admm_kernel(BoxArgs a) {
         for (int j = 0; j < NX; ++j) d += Kk[i * NX + j] * sx[j];
         su[i] = d;
         const double lo = a.lo[(size_t)k * NU + i], hi = a.hi[(size_t)k * NU + i];
-        const double zn = fmin(fmax(d + w[20 + i], lo), hi);
+        const double dr = kBoxRelax * d + (1.0 - kBoxRelax) * w[16 + i];  // over-relaxed du
+        const double zn = fmin(fmax(dr + w[20 + i], lo), hi);
         rp = fmax(rp, fabs(d - zn));
         rd = fmax(rd, a.rho * fabs(zn - w[16 + i]));
-        w[20 + i] += d - zn;
+        w[20 + i] += dr - zn;
         w[16 + i] = zn;
       }
       __syncthreads();
@@ -453,6 +462,10 @@ __global__ void __launch_bounds__(64) box_admm_kernel(BoxArgs a) {
         md = fmax(md, sres[1][i]);
       }
       sdone = (mp < a.tol && md < a.tol) ? 1 : 0;
+      if (a.resid) {
+        a.resid[(size_t)inst * 2] = mp;
+        a.resid[(size_t)inst * 2 + 1] = md;
+      }
     }
     __syncthreads();
     if (sdone) {
@@ -487,9 +500,9 @@ hipError_t launch_box_admm(int n_inst, const int* offsets, const float* A, const
                            const double* QN, const double* Rt, const double* q, const double* r, const double* qN,
                            const double* K, const double* P, const double* dx0, const double* lo, const double* hi,
                            double rho, double tol, int max_iter, double* ws, double* du, double* dx, double* dxN,
-                           int* iters, hipStream_t st) {
+                           int* iters, double* resid, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
-  BoxArgs a{offsets, A, B, c, QN, Rt, q, r, qN, K, P, dx0, lo, hi, rho, tol, max_iter, ws, du, dx, dxN, iters};
+  BoxArgs a{offsets, A, B, c, QN, Rt, q, r, qN, K, P, dx0, lo, hi, rho, tol, max_iter, ws, du, dx, dxN, iters, resid};
   box_admm_kernel<<<n_inst, 64, 0, st>>>(a);
   return hipGetLastError();
 }

@@ -724,7 +724,7 @@ extern "C" rtn_status rtn_riccati_box(int32_t n_inst, const int32_t* offsets_hos
                                       const double* QN_host, const double* q, const double* r, const double* qN,
                                       const double* dx0, const double* du_lo, const double* du_hi, double rho,
                                       int32_t max_iter, double tol, double* du, double* dx, double* dxN,
-                                      int32_t* iters, void* stream) {
+                                      int32_t* iters, double* resid, void* stream) {
   rtn_status s = check_offsets(n_inst, offsets_host, n_nodes);
   if (s) return s;
   if (!Q_host || !R_host || !QN_host) return fail(RTN_EINVAL, "Q_host, R_host and QN_host are required");
@@ -773,7 +773,7 @@ extern "C" rtn_status rtn_riccati_box(int32_t n_inst, const int32_t* offsets_hos
   if (e == hipSuccess) {
     ProfScope ps("box_admm", st);
     e = launch_box_admm(n_inst, doff, A, B, c, d + 185, d + 169, q, r, qN, K, P, dx0, du_lo, du_hi, rho, tol,
-                        max_iter, ws, du, dx, dxN, iters, st);
+                        max_iter, ws, du, dx, dxN, iters, resid, st);
   }
   hipError_t e2 = hipFreeAsync(dev, st);
   if (e != hipSuccess) return hip_fail(e, "rtn_riccati_box");

@@ -137,7 +137,7 @@ def test_riccati_box_validation(lib):
     qp = Q.ctypes.data_as(ctypes.c_void_p); rp = R.ctypes.data_as(ctypes.c_void_p)
     z = ctypes.c_void_p(16)
     args = lambda n, rho, it, tol, du=z: (1, None, n, z, z, None, qp, rp, qp, None, None, None, z, z, z,
-                                         rho, it, tol, du, None, None, None, None)
+                                         rho, it, tol, du, None, None, None, None, None)
     assert lib.rtn_riccati_box(*args(0, 1.0, 10, 1e-8)) == RTN_OK
     assert lib.rtn_riccati_box(*args(3, 0.0, 10, 1e-8)) == RTN_EINVAL       # rho
     assert lib.rtn_riccati_box(*args(3, float("nan"), 10, 1e-8)) == RTN_EINVAL

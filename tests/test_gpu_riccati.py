@@ -207,3 +207,40 @@ def test_prepared_call_matches_and_sees_new_data(torch):
         got = {k: v.cpu().numpy() for k, v in call().items()}
         K, kff, P = riccati_batched(off, A.astype(np.float64), B.astype(np.float64), Q, R, Q)
         assert rel_max(got["K"], K) < 1e-9 and rel_max(got["P"], P) < 1e-9
+
+
+@pytest.mark.parametrize("max_iter", [400, 4])
+def test_box_lq_flags_every_unconverged_instance(torch, max_iter):
+    """The box-constrained LQ of 4096 ragged instances (the benchmark's tolerance 1e-6,
+    rho 1, hover inputs in the box 0 <= u <= 4): every instance either converged --
+    fewer than max_iter iterations and both residuals of its last iteration below tol --
+    or reports max_iter iterations with the residual it stopped at.  With 4 iterations
+    most instances must be flagged, and the reported residual must be the one of the
+    returned inputs (the primal residual bounds how far du is from the box-feasible z)."""
+    import paper_2203_07747_amd as rtn
+    hz = sample_horizons(4096, 10, 50, seed=31)
+    off = offsets_from_horizons(hz)
+    n = int(off[-1])
+    from workload import sample_nodes
+    x, u = sample_nodes(n, seed=32)
+    print(f"[gpu] riccati_box flags n={n} max_iter={max_iter}", flush=True)
+    lin = rtn.linearize(torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda(), None, "fp32", 0.05, offsets=off)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    dx0 = torch.randn((len(hz), 13), device="cuda", dtype=torch.float64, generator=g) * 0.5
+    uk = torch.full((n, 4), 9.81 / 4, device="cuda", dtype=torch.float64)
+    out = rtn.riccati_box(lin["A"], lin["B"], np.eye(13), 0.1 * np.eye(4), np.eye(13), dx0, (-uk).contiguous(),
+                          (4.0 - uk).contiguous(), offsets=off, rho=1.0, max_iter=max_iter, tol=1e-6)
+    torch.cuda.synchronize()
+    it = out["iters"].cpu().numpy()
+    rs = out["resid"].cpu().numpy()
+    du = out["du"].cpu().numpy()
+    assert np.all(np.isfinite(rs)) and np.all(rs >= 0) and np.all(np.isfinite(du))
+    conv = it < max_iter
+    assert np.all(rs[conv].max(axis=1) < 1e-6)
+    flagged = ~conv
+    print(f"  iterations max {it.max()} median {np.median(it)}; flagged {int(flagged.sum())} of {len(hz)}; "
+          f"largest residual {rs.max():.2e}", flush=True)
+    assert np.all(it[flagged] == max_iter)
+    assert np.all((du >= -9.81 / 4 - 1e-12) & (du <= 4.0 - 9.81 / 4 + 1e-12))
+    if max_iter == 4:
+        assert flagged.sum() > len(hz) // 2 and rs[flagged].max() >= 1e-6

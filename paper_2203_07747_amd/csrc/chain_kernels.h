@@ -24,6 +24,8 @@
 // (L * H values per node).
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "mlp_chain.h"
 
@@ -424,43 +426,52 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
       const float* bias = net.bias[layer];
       S* st = stash + (size_t)layer * n * H;
       float lmax = 0.f;  // calibration: this lane's max |h|
+      // The activation is chosen once per layer, not per value: a branch inside the
+      // 16-value loop would serialise each value's exp -> rcp -> product chain.
+      auto tiles = [&](auto silu) __attribute__((always_inline)) {
 #pragma unroll
-      for (int i = 0; i < C::MTW; ++i) {
-        const int mt = wave * C::MTW + i;
-        float bm[16];
+        for (int i = 0; i < C::MTW; ++i) {
+          const int mt = wave * C::MTW + i;
+          float bm[16];
 #pragma unroll
-        for (int vi = 0; vi < 16; ++vi) bm[vi] = bias[mt * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3)];
+          for (int vi = 0; vi < 16; ++vi) bm[vi] = bias[mt * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3)];
 #pragma unroll
-        for (int r = 0; r < C::RT; ++r) {
-          const int row = row0 + r * 32 + (lane & 31);
-          float h[16], sp[16];
+          for (int r = 0; r < C::RT; ++r) {
+            const int row = row0 + r * 32 + (lane & 31);
+            float h[16], sp[16];
 #pragma unroll
-          for (int vi = 0; vi < 16; ++vi) {
-            const float a = acc[i][r][vi] * scale + bm[vi];
-            if (net.act == 0) {
-              const float sg = __builtin_amdgcn_rcpf(1.f + __expf(-a));
-              h[vi] = a * sg;
-              sp[vi] = sg * (1.f + a * (1.f - sg));
-            } else {
-              h[vi] = a;
-              sp[vi] = 1.f;
+            for (int vi = 0; vi < 16; ++vi) {
+              const float a = acc[i][r][vi] * scale + bm[vi];
+              if constexpr (decltype(silu)::value) {
+                // SiLU h = a s(a), s = logistic; act' = s (1 + a (1 - s)) = s + h (1 - s)
+                const float sg = __builtin_amdgcn_rcpf(1.f + __expf(-a));
+                h[vi] = a * sg;
+                sp[vi] = __builtin_fmaf(h[vi], 1.f - sg, sg);
+              } else {
+                h[vi] = a;
+                sp[vi] = 1.f;
+              }
             }
-          }
-          if (amax && row < n) {
+            if (amax && row < n) {
 #pragma unroll
-            for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(h[vi]));
-          }
-          if (row < n) store16<S>(st + (size_t)row * H + mt * 32 + g * 16, sp);
-          if (hsave && row < n) {  // training: h_l in natural feature order
-            float* hd = hsave + ((size_t)layer * n + row) * H + mt * 32 + g * 4;
+              for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(h[vi]));
+            }
+            if (row < n) store16<S>(st + (size_t)row * H + mt * 32 + g * 16, sp);
+            if (hsave && row < n) {  // training: h_l in natural feature order
+              float* hd = hsave + ((size_t)layer * n + row) * H + mt * 32 + g * 4;
 #pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4)
-              reinterpret_cast<float4*>(hd + q4 * 8)[0] =
-                  make_float4(h[4 * q4], h[4 * q4 + 1], h[4 * q4 + 2], h[4 * q4 + 3]);
+              for (int q4 = 0; q4 < 4; ++q4)
+                reinterpret_cast<float4*>(hd + q4 * 8)[0] =
+                    make_float4(h[4 * q4], h[4 * q4 + 1], h[4 * q4 + 2], h[4 * q4 + 3]);
+            }
+            C::put_operand(lds, r, mt, lane, h, inv_next);
           }
-          C::put_operand(lds, r, mt, lane, h, inv_next);
         }
-      }
+      };
+      if (net.act == 0)
+        tiles(std::true_type{});
+      else
+        tiles(std::false_type{});
       if (amax) atomic_amax(&amax[layer + 1], lmax);
       __syncthreads();
     }
@@ -573,17 +584,26 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
       // of these reads otherwise dominate this phase.  Rows past the end are
       // written as zeros.
       constexpr int NU = C::KS_H * 2 * kDout * 4;
+      constexpr int UPT = (NU + NT - 1) / NT;  // units per thread
       const int jr = row0 % 6;
-#pragma unroll 1
-      for (int u = tid; u < NU; u += NT) {
-        const int qr = u & 3, j = (u >> 2) % kDout, gg = (u / (4 * kDout)) & 1, sk = u / (8 * kDout);
-        float wv[C::E];
+      // every unit's weights are requested before the first unit's rows are built
+      float wv[UPT][C::E];
+#pragma unroll
+      for (int k = 0; k < UPT; ++k) {
+        const int u = tid + k * NT;
+        const int j = (u >> 2) % kDout, gg = (u / (4 * kDout)) & 1, sk = min(u, NU - 1) / (8 * kDout);
 #pragma unroll
         for (int run = 0; run < C::E / RL; ++run) {
           const int q0 = sk * C::E + run * RL;
           const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);  // stash order of slot q0
-          load_run<RL>(wo + j * wo_stride + pos, wv + run * RL);
+          load_run<RL>(wo + j * wo_stride + pos, wv[k] + run * RL);
         }
+      }
+#pragma unroll
+      for (int k = 0; k < UPT; ++k) {
+        const int u = tid + k * NT;
+        if (u >= NU) break;
+        const int qr = u & 3, j = (u >> 2) % kDout, gg = (u / (4 * kDout)) & 1, sk = u / (8 * kDout);
         // block rows i with (row0 + i) % 6 == j, this quarter: i = i0 + 6 qr + 24 m
         const int i0 = (j - jr + 6) % 6 + 6 * qr;
 #pragma unroll 2
@@ -599,7 +619,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
             load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, v + run * RL);
           }
 #pragma unroll
-          for (int t = 0; t < C::E; ++t) v[t] = live ? wv[t] * v[t] : 0.f;
+          for (int t = 0; t < C::E; ++t) v[t] = live ? wv[k][t] * v[t] : 0.f;
           if (amax) {
 #pragma unroll
             for (int t = 0; t < C::E; ++t) lmax = fmaxf(lmax, fabsf(v[t]));

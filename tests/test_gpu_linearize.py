@@ -436,7 +436,7 @@ def test_autotuner_keeps_a_valid_choice_and_results_match(torch):
     assert got is not None
     choice, ms = got
     print(f"  kept {choice}, forward {ms[0]:.3f} ms, reverse {ms[1]:.3f} ms", flush=True)
-    assert choice[0] == 0 and choice[1] in (0, 1, 2) and choice[3] in (0, 1, 2, 3) and min(choice) >= 0
+    assert choice[0] == 0 and 0 <= choice[1] <= 4 and 0 <= choice[3] <= 4 and min(choice) >= 0
     assert ms[0] > 0 and ms[1] > 0
     ref = linearize_affine(x[:20], u[:20], MLP(Ws, bs), DT)
     res = {k: v.cpu().numpy() for k, v in out.items()}

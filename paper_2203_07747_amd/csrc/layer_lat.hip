@@ -489,8 +489,8 @@ __global__ void __launch_bounds__(kFzThreads) lat_fused_kernel(LatNet net, int n
     }
   }
   if (with_rk4)  // uniform; the routine's first barrier publishes rs
-    rk4_block(rs, reinterpret_cast<int*>(rs + kNodesPerBlock * kNodeStride), nn, node0, t, rk.P, rk.dt, true, rk.xn,
-              rk.A, rk.B, rk.status, net.input);
+    rk4_block_lanes(rs, reinterpret_cast<int*>(rs + kNodesPerBlock * kNodeStride), nn, node0, t, rk.P, rk.dt, true,
+                    rk.xn, rk.A, rk.B, rk.status, net.input);
 }
 
 bool lat_fused_fits(const LatNet& net) { return net.H == kFzH && net.L >= 1 && net.L <= kFzMaxL; }
@@ -523,7 +523,7 @@ hipError_t launch_lat_fused(const LatNet& net, int n, const float* x, const floa
 // contiguous quarters of the wave's K range, so that every lane reads its
 // operand rows as float4.  Rows past the block's last node repeat its last row
 // (valid addresses) and are dropped.  Partial tiles are summed in LDS in fixed
-// wave order, then handed to rk4_block with the node data.
+// wave order, then handed to rk4_block_lanes with the node data.
 constexpr int kTlThreads = 512, kTlTiles = kDout + 1;
 
 template <int S>  // K-steps per lane: H = 32 S
@@ -591,8 +591,8 @@ __global__ void __launch_bounds__(kTlThreads)
       rs[row * kNodeStride + 17 + col] = yv;
     }
   }
-  rk4_block(rs, reinterpret_cast<int*>(rs + kNodesPerBlock * kNodeStride), nn, node0, t, rk.P, rk.dt, true, rk.xn,
-            rk.A, rk.B, rk.status, input);
+  rk4_block_lanes(rs, reinterpret_cast<int*>(rs + kNodesPerBlock * kNodeStride), nn, node0, t, rk.P, rk.dt, true,
+                  rk.xn, rk.A, rk.B, rk.status, input);
 }
 
 bool lat_tail_fits(const LatNet& net) {

@@ -9,7 +9,8 @@
 //   [A | B] = d x_{k+1} / d [x_k, u_k], carried as 13-vector tangents through the
 //   four stages:  dk_s = (df_F/dx + J_x) dx_s  (+ df_F/du_j + J_u e_j for input j).
 //
-// The per-node routine and its work split (16 lanes per node) are in rk4_node.h.
+// The per-node routine and its work split (one lane per node for the state,
+// 16 per node for the tangents) are in rk4_node.h.
 #include "common.h"
 #include "mlp_chain.h"
 #include "quad_model.h"
@@ -17,32 +18,39 @@
 
 namespace rtn {
 
-__global__ void __launch_bounds__(256)
+// 64 nodes per workgroup: phase (1) of rk4_block then fills one wave.
+constexpr int kRk4Nodes = 64, kRk4Threads = 256;
+
+__global__ void __launch_bounds__(kRk4Threads)
 rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, const float* __restrict__ u,
                      const float* __restrict__ fD, const float* __restrict__ JD, float* __restrict__ xn,
                      float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status, int input) {
-  __shared__ float sm[kNodesPerBlock * kNodeStride];
-  __shared__ int flags[kNodesPerBlock];
+  __shared__ float sm[kRk4Nodes * kNodeStride];
+  __shared__ float tr[kRk4Nodes * kTrajStride];
+  __shared__ int flags[kRk4Nodes];
   const int tid = threadIdx.x;
-  const int node0 = blockIdx.x * kNodesPerBlock;
-  const int nn = min(kNodesPerBlock, n - node0);
+  const int node0 = blockIdx.x * kRk4Nodes;
+  const int nn = min(kRk4Nodes, n - node0);
   if (nn <= 0) return;
   // cooperative, coalesced staging of the block's node data
-  for (int i = tid; i < nn * kNx; i += 256) sm[(i / kNx) * kNodeStride + (i % kNx)] = x[(size_t)node0 * kNx + i];
-  for (int i = tid; i < nn * kNu; i += 256) sm[(i / kNu) * kNodeStride + 13 + (i % kNu)] = u[(size_t)node0 * kNu + i];
-  for (int i = tid; i < nn * kDout; i += 256)
+  for (int i = tid; i < nn * kNx; i += kRk4Threads)
+    sm[(i / kNx) * kNodeStride + (i % kNx)] = x[(size_t)node0 * kNx + i];
+  for (int i = tid; i < nn * kNu; i += kRk4Threads)
+    sm[(i / kNu) * kNodeStride + 13 + (i % kNu)] = u[(size_t)node0 * kNu + i];
+  for (int i = tid; i < nn * kDout; i += kRk4Threads)
     sm[(i / kDout) * kNodeStride + 17 + (i % kDout)] = fD ? fD[(size_t)node0 * kDout + i] : 0.f;
-  for (int i = tid; i < nn * kDout * kDin; i += 256)
-    sm[(i / (kDout * kDin)) * kNodeStride + 23 + (i % (kDout * kDin))] = JD ? JD[(size_t)node0 * kDout * kDin + i] : 0.f;
-  rk4_block(sm, flags, nn, node0, tid, P, dt, JD != nullptr, xn, A, B, status, input);
+  for (int i = tid; i < nn * kDout * kDin; i += kRk4Threads)
+    sm[(i / (kDout * kDin)) * kNodeStride + 23 + (i % (kDout * kDin))] =
+        JD ? JD[(size_t)node0 * kDout * kDin + i] : 0.f;
+  rk4_block(sm, tr, flags, nn, node0, tid, kRk4Threads, P, dt, JD != nullptr, xn, A, B, status, input);
 }
 
 hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
                                 const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st,
                                 int input) {
   if (n <= 0) return hipSuccess;
-  const int blocks = (n + kNodesPerBlock - 1) / kNodesPerBlock;
-  rk4_linearize_kernel<<<blocks, 256, 0, st>>>(n, q, dt, x, u, fD, JD, xn, A, B, status, input);
+  const int blocks = (n + kRk4Nodes - 1) / kRk4Nodes;
+  rk4_linearize_kernel<<<blocks, kRk4Threads, 0, st>>>(n, q, dt, x, u, fD, JD, xn, A, B, status, input);
   return hipGetLastError();
 }
 

@@ -604,27 +604,35 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
         const int u = tid + k * NT;
         if (u >= NU) break;
         const int qr = u & 3, j = (u >> 2) % kDout, gg = (u / (4 * kDout)) & 1, sk = u / (8 * kDout);
-        // block rows i with (row0 + i) % 6 == j, this quarter: i = i0 + 6 qr + 24 m
+        // block rows i with (row0 + i) % 6 == j, this quarter: i = i0 + 6 qr + 24 m;
+        // all of the unit's rows are read before the first is written (the
+        // operand stores would otherwise hold back every following read)
         const int i0 = (j - jr + 6) % 6 + 6 * qr;
-#pragma unroll 2
-        for (int i = i0; i < R; i += 24) {
-          const int row = row0 + i;
-          const bool live = row < nrows;
-          const int node = live ? row / 6 : node0;
-          float v[C::E];
+        constexpr int NI = (R + 23) / 24;
+        float v[NI][C::E];
+#pragma unroll
+        for (int m = 0; m < NI; ++m) {
+          const int row = row0 + i0 + 24 * m;
+          const int node = (i0 + 24 * m < R && row < nrows) ? row / 6 : node0;
 #pragma unroll
           for (int run = 0; run < C::E / RL; ++run) {
             const int q0 = sk * C::E + run * RL;
             const int pos = 32 * (q0 >> 4) + gg * 16 + (q0 & 15);
-            load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, v + run * RL);
+            load_run<RL>(sp_lds + (node - node0) * C::SPS + pos, v[m] + run * RL);
           }
+        }
 #pragma unroll
-          for (int t = 0; t < C::E; ++t) v[t] = live ? wv[k][t] * v[t] : 0.f;
+        for (int m = 0; m < NI; ++m) {
+          const int i = i0 + 24 * m;
+          if (i >= R) break;
+          const bool live = row0 + i < nrows;
+#pragma unroll
+          for (int t = 0; t < C::E; ++t) v[m][t] = live ? wv[k][t] * v[m][t] : 0.f;
           if (amax) {
 #pragma unroll
-            for (int t = 0; t < C::E; ++t) lmax = fmaxf(lmax, fabsf(v[t]));
+            for (int t = 0; t < C::E; ++t) lmax = fmaxf(lmax, fabsf(v[m][t]));
           }
-          C::put_slots(lds, i >> 5, sk, gg * 32 + (i & 31), C::KS_H, v, inv);
+          C::put_slots(lds, i >> 5, sk, gg * 32 + (i & 31), C::KS_H, v[m], inv);
         }
       }
       if (amax) atomic_amax(&amax[L - 1], lmax);
@@ -645,7 +653,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
       // activation-derivative runs (16 stash values = 32 or 64 bytes each, kept
       // packed) before their first use
       constexpr bool PRE = C::kOcc == 1 && C::MTW * C::RT <= 12;
-      constexpr int PI = PRE ? C::MTW : 1, PR = PRE ? C::RT : 1;
+      constexpr int PI = PRE ? C::MTW : 1, PR = PRE ? C::RT : 2;
       constexpr int RUN_CH = 16 * (int)sizeof(S) / 16;  // 16-byte chunks per run
       i32x4 spraw[PI][PR][RUN_CH];
       auto raw_load = [&](int i, int r, int mt, int row) {
@@ -659,6 +667,10 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
         for (int i = 0; i < C::MTW; ++i)
 #pragma unroll
           for (int r = 0; r < C::RT; ++r) raw_load(i, r, wave * C::MTW + i, row0 + r * 32 + (lane & 31));
+      } else {
+        // otherwise each run is read one tile ahead, before the previous tile's
+        // operand stores (which the compiler cannot move loads across)
+        raw_load(0, 0, wave * C::MTW, row0 + (lane & 31));
       }
 #pragma unroll
       for (int i = 0; i < C::MTW; ++i) {
@@ -666,8 +678,14 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
 #pragma unroll
         for (int r = 0; r < C::RT; ++r) {
           const int row = row0 + r * 32 + (lane & 31);
-          const int pi = PRE ? i : 0, pr = PRE ? r : 0;
-          if constexpr (!PRE) raw_load(0, 0, mt, row);
+          const int t = i * C::RT + r;
+          const int pi = PRE ? i : 0, pr = PRE ? r : (t & 1);
+          if constexpr (!PRE) {
+            if (t + 1 < C::MTW * C::RT) {
+              const int i1 = (t + 1) / C::RT, r1 = (t + 1) % C::RT;
+              raw_load(0, (t + 1) & 1, wave * C::MTW + i1, row0 + r1 * 32 + (lane & 31));
+            }
+          }
           float sv[16];
           load_run<16>(reinterpret_cast<const S*>(spraw[pi][pr]), sv);
           float v[16];

@@ -3,9 +3,11 @@
 // With a single MPC instance (tens of nodes) the layer-chain kernels run on a
 // handful of compute units: one workgroup carries a block of rows through all
 // layers.  Here every layer is its own launch instead and spreads its output
-// features over many workgroups (32 x 32 output tiles) and its reduction over up
-// to 16 waves per workgroup, so a layer of 20 nodes x 512 features still
-// occupies 16-64 compute units.  Same mathematics as the chain kernels
+// features over many workgroups (32 x 32 output tiles, 16 x 16 when that grid
+// would be small) and its reduction over up to 16 waves per workgroup, so a
+// layer of 20 nodes x 512 features still occupies 64-256 compute units.  The
+// output layer and J_D are launches of the same kind; the RK4 step follows
+// (launch_rk4_lanes).  Same mathematics as the chain kernels
 // (Sec. IV-A: network value and reverse-mode Jacobian once per node):
 //   forward : h_l = SiLU(W_l h_{l-1} + b_l), act'(a_l) kept; y = W_{L+1} h_L + b_{L+1}
 //   reverse : G_L = W_{L+1} (.) act'(a_L) (6 rows per node, formed while loading);
@@ -54,7 +56,9 @@ struct LatArgs {
   int input;                   // LA_Z0: network input variant (net_feature)
 };
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kLatWaves = 16;
+constexpr int kLatNarrowBelow = 128;  // 32 x 32 tiles of a launch below which 16 x 16 tiles are used
 
 __device__ inline float lat_a(const LatArgs& p, int akind, int r, int k) {
   if (r >= p.M || k >= p.K) return 0.f;
@@ -87,6 +91,31 @@ __device__ inline float4 lat_b4(const LatArgs& p, int bkind, int k, int c) {
   if (bkind == LB_NT) return *reinterpret_cast<const float4*>(p.W + (size_t)c * p.K + k);
   const float* w = p.W + (size_t)k * p.N + c;
   return make_float4(w[0], w[p.N], w[2 * (size_t)p.N], w[3 * (size_t)p.N]);
+}
+
+// Epilogue of one output element (row, col) with the reduced product s.
+template <int EP> __device__ inline void lat_store(const LatArgs& p, int row, int col, float s) {
+  const size_t o = (size_t)row * p.N + col;
+  if constexpr (EP == LE_SILU) {
+    const float a = s + p.bias[col];
+    if (p.act == 0) {
+      const float sg = 1.f / (1.f + __expf(-a));
+      p.out[o] = a * sg;
+      p.dout[o] = sg * (1.f + a * (1.f - sg));
+      if (p.ddout) p.ddout[o] = sg * (1.f - sg) * (2.f + a * (1.f - 2.f * sg));
+    } else {
+      p.out[o] = a;
+      p.dout[o] = 1.f;
+      if (p.ddout) p.ddout[o] = 0.f;
+    }
+  } else if constexpr (EP == LE_BIAS) {
+    p.out[o] = s + p.bias[col];
+  } else if constexpr (EP == LE_GATE) {
+    p.out[o] = s * p.gate[(size_t)(row / 6) * p.N + col];
+    if (p.dout) p.dout[o] = s;
+  } else {
+    p.out[o] = s;
+  }
 }
 
 // One 32 x 32 output tile per workgroup, the K-steps split over its waves
@@ -145,39 +174,95 @@ __global__ void __launch_bounds__(kLatWaves * kWave) lat_layer(LatArgs p) {
     float s = 0.f;
     for (int w = 0; w < nw; ++w) s += part[w][rr * 33 + cc];
     if (row >= p.M || col >= p.N) continue;
-    const size_t o = (size_t)row * p.N + col;
-    if constexpr (EP == LE_SILU) {
-      const float a = s + p.bias[col];
-      if (p.act == 0) {
-        const float sg = 1.f / (1.f + __expf(-a));
-        p.out[o] = a * sg;
-        p.dout[o] = sg * (1.f + a * (1.f - sg));
-        if (p.ddout) p.ddout[o] = sg * (1.f - sg) * (2.f + a * (1.f - 2.f * sg));
-      } else {
-        p.out[o] = a;
-        p.dout[o] = 1.f;
-        if (p.ddout) p.ddout[o] = 0.f;
+    lat_store<EP>(p, row, col, s);
+  }
+}
+
+// Narrow form for small grids: one 16 x 16 output tile per workgroup (MFMA
+// 16x16x4 fp32).  A layer of a few tens of rows is bound by how fast each
+// compute unit pulls its operands in (tens of GB/s per unit at these latencies),
+// so a quarter of the tile area spreads the layer over four times as many units,
+// each moving half the operand bytes of a 32 x 32 tile.  K is split over the
+// waves; lane l supplies row / column l % 16 at k slot l / 16.  Scalar path: wave
+// w takes 4-k steps w, w + nw, ...; VEC path (K a multiple of 16 nw, aligned
+// operands): the four k slots run over four contiguous quarters of the wave's K
+// range, so every lane reads its operand row as float4.
+template <int AK, int BK, int EP, bool VEC>
+__global__ void __launch_bounds__(kLatWaves * kWave) lat_layer16(LatArgs p) {
+  __shared__ float part[kLatWaves][16 * 17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int r = blockIdx.y * 16 + li, c = blockIdx.x * 16 + li;
+  f32x4 acc = {};
+  constexpr int MAXS = 16;  // MFMA steps per wave: K <= 4 * 16 * 16 = 1024
+  float av[MAXS], bv[MAXS];
+  if constexpr (VEC) {
+    const int QW = p.K / nw / 4, kb = wave * (p.K / nw) + kq * QW;
+#pragma unroll
+    for (int j = 0; j < MAXS / 4; ++j) {
+      float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4;
+      if (4 * j < QW) {
+        a4 = lat_a4(p, AK, r, kb + 4 * j);
+        b4 = lat_b4(p, BK, kb + 4 * j, c);
       }
-    } else if constexpr (EP == LE_BIAS) {
-      p.out[o] = s + p.bias[col];
-    } else if constexpr (EP == LE_GATE) {
-      p.out[o] = s * p.gate[(size_t)(row / 6) * p.N + col];
-      if (p.dout) p.dout[o] = s;
-    } else {
-      p.out[o] = s;
+      av[4 * j] = a4.x, av[4 * j + 1] = a4.y, av[4 * j + 2] = a4.z, av[4 * j + 3] = a4.w;
+      bv[4 * j] = b4.x, bv[4 * j + 1] = b4.y, bv[4 * j + 2] = b4.z, bv[4 * j + 3] = b4.w;
     }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+      if (i < QW) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
+  } else {
+    const int ksteps = (p.K + 3) / 4;
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+      const int s = wave + i * nw;
+      const int k = 4 * s + kq;
+      const bool live = s < ksteps;
+      av[i] = live ? lat_a(p, AK, r, k) : 0.f;
+      bv[i] = live ? lat_b(p, BK, k, c) : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i)
+      if (wave + i * nw < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
+  }
+  // accumulator v of lane l: row 4 (l / 16) + v, column l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[wave][(4 * kq + v) * 17 + li] = acc[v];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * 16; e += blockDim.x) {
+    const int rr = e >> 4, cc = e & 15, row = blockIdx.y * 16 + rr, col = blockIdx.x * 16 + cc;
+    float s = 0.f;
+    for (int w = 0; w < nw; ++w) s += part[w][rr * 17 + cc];
+    if (row >= p.M || col >= p.N) continue;
+    lat_store<EP>(p, row, col, s);
   }
 }
 
 template <int AK, int BK, int EP> static hipError_t lat_launch(const LatArgs& p, hipStream_t st) {
   if (p.M <= 0 || p.N <= 0) return hipSuccess;
   if (p.K > 2 * kLatWaves * 32) return hipErrorInvalidValue;
+  auto al16 = [](const void* q) { return q == nullptr || reinterpret_cast<uintptr_t>(q) % 16 == 0; };
+  if (((p.N + 31) / 32) * ((p.M + 31) / 32) < kLatNarrowBelow && p.K <= 4 * kLatWaves * 16) {
+    const dim3 grid((p.N + 15) / 16, (p.M + 15) / 16);
+    int nw = (p.K / 4 + 15) / 16;  // about 16 MFMA steps per wave
+    if (nw > kLatWaves) nw = kLatWaves;
+    if (nw < 4) nw = 4;  // (the epilogue runs on the same waves)
+    const bool vec = p.K % (16 * nw) == 0 && al16(p.A) && al16(p.gate_a) && al16(p.W) &&
+                     (AK != LA_GOUT || (p.wk == 1 && p.wj % 4 == 0 && al16(p.wsrc)));
+    if constexpr (AK != LA_Z0) {
+      if (vec) {
+        lat_layer16<AK, BK, EP, true><<<grid, nw * kWave, 0, st>>>(p);
+        return hipGetLastError();
+      }
+    }
+    lat_layer16<AK, BK, EP, false><<<grid, nw * kWave, 0, st>>>(p);
+    return hipGetLastError();
+  }
   const int ksteps = (p.K + 1) / 2;
   int nw = (ksteps + 15) / 16;  // about 16 K-steps per wave, at most 16 waves
   if (nw > kLatWaves) nw = kLatWaves;
   if (nw < 1) nw = 1;
   dim3 grid((p.N + 31) / 32, (p.M + 31) / 32);
-  auto al16 = [](const void* q) { return q == nullptr || reinterpret_cast<uintptr_t>(q) % 16 == 0; };
   const bool vec = p.K % 8 == 0 && ksteps % nw == 0 && (ksteps / nw) % 4 == 0 && al16(p.A) && al16(p.gate_a) &&
                    al16(p.W) && (AK != LA_GOUT || (p.wk == 1 && p.wj % 4 == 0 && al16(p.wsrc)));
   if constexpr (AK != LA_Z0) {  // the input features are formed, not loaded
@@ -212,7 +297,7 @@ hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const fl
     e = l == 0 ? lat_launch<LA_Z0, LB_NT, LE_SILU>(p, st) : lat_launch<LA_ACT, LB_NT, LE_SILU>(p, st);
     if (e != hipSuccess) return e;
   }
-  if (!y) return hipSuccess;  // the value is formed by the tail kernel
+  if (!y) return hipSuccess;
   LatArgs p{};
   p.M = n;
   p.N = kDout;
@@ -252,7 +337,7 @@ hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* 
     }
     if (e != hipSuccess) return e;
   }
-  if (!J) return hipSuccess;  // J_D is formed by the tail kernel (from G_1 in g + M H)
+  if (!J) return hipSuccess;
   LatArgs p{};
   p.M = M;
   p.N = kDin;
@@ -282,7 +367,6 @@ hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* 
 // (value, Jacobian and node data handed over in LDS).
 constexpr int kFzNodes = 16, kFzH = 64, kFzMaxL = 4, kFzThreads = 512;
 constexpr int kFzS = kFzH + 1, kFzW0S = kDin + 1, kFzRows = kFzNodes * kDout;  // 96 cotangent rows
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 static_assert(kFzNodes == kNodesPerBlock, "one RK4 block per workgroup");
 
@@ -511,113 +595,6 @@ hipError_t launch_lat_fused(const LatNet& net, int n, const float* x, const floa
   }
   lat_fused_kernel<<<(n + kFzNodes - 1) / kFzNodes, kFzThreads, fz_lds_bytes(net.L), st>>>(net, n, x, u, y, J,
                                                                                      rk4 ? *rk4 : FusedRk4{});
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Tail of the per-layer path (width 128..1024, L >= 2): J_D = G_1 W_1, the value
-// y = W_{L+1} h_L + b_{L+1} and the RK4 step of 16 nodes in one workgroup --
-// one launch instead of three.  The six 16-row tiles of J_D (96 rows = 16 nodes
-// x 6 outputs) and the 16-node tile of y run on MFMA 16x16x4 fp32 with K split
-// over the 8 waves; within a wave the four k slots of a product run over four
-// contiguous quarters of the wave's K range, so that every lane reads its
-// operand rows as float4.  Rows past the block's last node repeat its last row
-// (valid addresses) and are dropped.  Partial tiles are summed in LDS in fixed
-// wave order, then handed to rk4_block_lanes with the node data.
-constexpr int kTlThreads = 512, kTlTiles = kDout + 1;
-
-template <int S>  // K-steps per lane: H = 32 S
-__global__ void __launch_bounds__(kTlThreads)
-    lat_tail_kernel(int n, const float* __restrict__ hL, const float* __restrict__ G1, const float* __restrict__ W1,
-                    const float* __restrict__ Wo, const float* __restrict__ bo, const float* __restrict__ x,
-                    const float* __restrict__ u, float* __restrict__ y, float* __restrict__ J, FusedRk4 rk,
-                    int input) {
-  constexpr int H = 32 * S, CH = S < 16 ? S : 16;
-  __shared__ float part[kTlThreads / kWave][kTlTiles][256];
-  __shared__ float rs[kNodesPerBlock * kNodeStride + kNodesPerBlock];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, r = lane & 15, kq = lane >> 4;
-  const int node0 = blockIdx.x * kNodesPerBlock, nn = min(kNodesPerBlock, n - node0), rows = nn * kDout;
-  if (t < nn * kNx) rs[(t / kNx) * kNodeStride + t % kNx] = x[(size_t)node0 * kNx + t];
-  if (t < nn * kNu) rs[(t >> 2) * kNodeStride + 13 + (t & 3)] = u[(size_t)node0 * kNu + t];
-  const int kl = wave * (H / 8) + kq * S;  // this lane's k run [kl, kl + S)
-  const float* arow[kTlTiles];
-#pragma unroll
-  for (int rt = 0; rt < kDout; ++rt) arow[rt] = G1 + ((size_t)node0 * kDout + min(rt * 16 + r, rows - 1)) * H + kl;
-  arow[kDout] = hL + ((size_t)node0 + min(r, nn - 1)) * H + kl;
-  const float* wy = Wo + (size_t)min(r, kDout - 1) * H + kl;  // columns r >= 6 (and >= 14 of J_D) are dropped
-  const float* wj = W1 + (size_t)kl * kDin + min(r, kDin - 1);
-  f32x4 acc[kTlTiles] = {};
-#pragma unroll
-  for (int c0 = 0; c0 < S; c0 += CH) {
-    float a[kTlTiles][CH], bj[CH], by[CH];
-#pragma unroll
-    for (int i = 0; i < CH; i += 4) {
-#pragma unroll
-      for (int rt = 0; rt < kTlTiles; ++rt) {
-        const float4 v = *reinterpret_cast<const float4*>(arow[rt] + c0 + i);
-        a[rt][i] = v.x, a[rt][i + 1] = v.y, a[rt][i + 2] = v.z, a[rt][i + 3] = v.w;
-      }
-      const float4 w = *reinterpret_cast<const float4*>(wy + c0 + i);
-      by[i] = w.x, by[i + 1] = w.y, by[i + 2] = w.z, by[i + 3] = w.w;
-    }
-#pragma unroll
-    for (int i = 0; i < CH; ++i) bj[i] = wj[(size_t)(c0 + i) * kDin];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-#pragma unroll
-      for (int rt = 0; rt < kDout; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][i], bj[i], acc[rt], 0, 0, 0);
-      acc[kDout] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kDout][i], by[i], acc[kDout], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int rt = 0; rt < kTlTiles; ++rt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) part[wave][rt][(4 * kq + v) * 16 + r] = acc[rt][v];
-  __syncthreads();
-  for (int e = t; e < kTlTiles * 256; e += kTlThreads) {
-    const int rt = e >> 8, el = e & 255, row = el >> 4, col = el & 15;
-    float sum = 0.f;
-#pragma unroll
-    for (int w = 0; w < kTlThreads / kWave; ++w) sum += part[w][rt][el];
-    if (rt < kDout) {
-      const int p = rt * 16 + row;
-      if (p < rows && col < kDin) {
-        J[((size_t)node0 * kDout + p) * kDin + col] = sum;
-        rs[(p / kDout) * kNodeStride + 23 + (p % kDout) * kDin + col] = sum;
-      }
-    } else if (row < nn && col < kDout) {
-      const float yv = sum + bo[col];
-      y[((size_t)node0 + row) * kDout + col] = yv;
-      rs[row * kNodeStride + 17 + col] = yv;
-    }
-  }
-  rk4_block_lanes(rs, reinterpret_cast<int*>(rs + kNodesPerBlock * kNodeStride), nn, node0, t, rk.P, rk.dt, true,
-                  rk.xn, rk.A, rk.B, rk.status, input);
-}
-
-bool lat_tail_fits(const LatNet& net) {
-  const int H = net.H;
-  return net.L >= 2 && (H == 128 || H == 256 || H == 512 || H == 1024) &&
-         reinterpret_cast<uintptr_t>(net.W[net.L]) % 16 == 0;
-}
-
-hipError_t launch_lat_tail(const LatNet& net, int n, const float* act, const float* g, const float* x, const float* u,
-                           float* y, float* J, const FusedRk4& rk, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  if (!lat_tail_fits(net)) return hipErrorInvalidValue;
-  const int L = net.L, H = net.H;
-  const float* hL = act + (size_t)((L - 1) & 1) * n * H;  // the forward pass's last activations
-  const float* G1 = g + (size_t)6 * n * H;                // the reverse sweep's G_1
-  const dim3 grid((n + kNodesPerBlock - 1) / kNodesPerBlock);
-#define RTN_TAIL(S_)                                                                                              \
-  lat_tail_kernel<S_><<<grid, kTlThreads, 0, st>>>(n, hL, G1, net.W[0], net.W[L], net.b[L], x, u, y, J, rk, net.input)
-  switch (H) {
-    case 128: RTN_TAIL(4); break;
-    case 256: RTN_TAIL(8); break;
-    case 512: RTN_TAIL(16); break;
-    default: RTN_TAIL(32); break;
-  }
-#undef RTN_TAIL
   return hipGetLastError();
 }
 

@@ -54,6 +54,35 @@ hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256)
+rk4_lanes_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, const float* __restrict__ u,
+                 const float* __restrict__ fD, const float* __restrict__ JD, float* __restrict__ xn,
+                 float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status, int input) {
+  __shared__ float sm[kNodesPerBlock * kNodeStride];
+  __shared__ int flags[kNodesPerBlock];
+  const int tid = threadIdx.x;
+  const int node0 = blockIdx.x * kNodesPerBlock;
+  const int nn = min(kNodesPerBlock, n - node0);
+  if (nn <= 0) return;
+  for (int i = tid; i < nn * kNx; i += 256) sm[(i / kNx) * kNodeStride + (i % kNx)] = x[(size_t)node0 * kNx + i];
+  for (int i = tid; i < nn * kNu; i += 256) sm[(i / kNu) * kNodeStride + 13 + (i % kNu)] = u[(size_t)node0 * kNu + i];
+  for (int i = tid; i < nn * kDout; i += 256)
+    sm[(i / kDout) * kNodeStride + 17 + (i % kDout)] = fD ? fD[(size_t)node0 * kDout + i] : 0.f;
+  for (int i = tid; i < nn * kDout * kDin; i += 256)
+    sm[(i / (kDout * kDin)) * kNodeStride + 23 + (i % (kDout * kDin))] =
+        JD ? JD[(size_t)node0 * kDout * kDin + i] : 0.f;
+  rk4_block_lanes(sm, flags, nn, node0, tid, P, dt, JD != nullptr, xn, A, B, status, input);
+}
+
+hipError_t launch_rk4_lanes(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,
+                            const float* JD, float* xn, float* A, float* B, uint8_t* status, hipStream_t st,
+                            int input) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + kNodesPerBlock - 1) / kNodesPerBlock;
+  rk4_lanes_kernel<<<blocks, 256, 0, st>>>(n, q, dt, x, u, fD, JD, xn, A, B, status, input);
+  return hipGetLastError();
+}
+
 }  // namespace rtn
 
 namespace rtn {

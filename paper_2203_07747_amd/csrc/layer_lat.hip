@@ -5,9 +5,8 @@
 // layers.  Here every layer is its own launch instead and spreads its output
 // features over many workgroups (32 x 32 output tiles, 16 x 16 when that grid
 // would be small) and its reduction over up to 16 waves per workgroup, so a
-// layer of 20 nodes x 512 features still occupies 64-256 compute units.  The
-// output layer and J_D are launches of the same kind; the RK4 step follows
-// (launch_rk4_lanes).  Same mathematics as the chain kernels
+// layer of 20 nodes x 512 features still occupies 64-256 compute units.  J_D,
+// the output layer and the RK4 step follow in one launch (lat_tail_kernel).  Same mathematics as the chain kernels
 // (Sec. IV-A: network value and reverse-mode Jacobian once per node):
 //   forward : h_l = SiLU(W_l h_{l-1} + b_l), act'(a_l) kept; y = W_{L+1} h_L + b_{L+1}
 //   reverse : G_L = W_{L+1} (.) act'(a_L) (6 rows per node, formed while loading);
@@ -297,7 +296,7 @@ hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const fl
     e = l == 0 ? lat_launch<LA_Z0, LB_NT, LE_SILU>(p, st) : lat_launch<LA_ACT, LB_NT, LE_SILU>(p, st);
     if (e != hipSuccess) return e;
   }
-  if (!y) return hipSuccess;
+  if (!y) return hipSuccess;  // (the tail kernel forms it)
   LatArgs p{};
   p.M = n;
   p.N = kDout;
@@ -337,7 +336,7 @@ hipError_t launch_lat_reverse(const LatNet& net, int n, const float* sp, float* 
     }
     if (e != hipSuccess) return e;
   }
-  if (!J) return hipSuccess;
+  if (!J) return hipSuccess;  // (the tail kernel forms it from G_1 in g + M H)
   LatArgs p{};
   p.M = M;
   p.N = kDin;
@@ -595,6 +594,119 @@ hipError_t launch_lat_fused(const LatNet& net, int n, const float* x, const floa
   }
   lat_fused_kernel<<<(n + kFzNodes - 1) / kFzNodes, kFzThreads, fz_lds_bytes(net.L), st>>>(net, n, x, u, y, J,
                                                                                      rk4 ? *rk4 : FusedRk4{});
+  return hipGetLastError();
+}
+
+// Tail of the per-layer path (width 128..1024, L >= 2): J_D = G_1 W_1, the value
+// y = W_{L+1} h_L + b_{L+1} and the RK4 step of kTlNodes nodes in one workgroup --
+// one launch instead of three.  Each workgroup reads G_1's rows of its nodes
+// (6 per node), their h_L rows and all of W_1 and W_{L+1}; at a few nodes per
+// workgroup these reads, not the arithmetic, set the time, so the nodes are
+// spread thin over the workgroups.  The 16-row tiles of J_D and the tile of y
+// run on MFMA 16x16x4 fp32 with K split over the 8 waves; within a wave the
+// four k slots of a product run over four contiguous quarters of the wave's K
+// range, so that every lane reads its operand rows as float4.  Rows past the
+// block's last node repeat its last row (valid addresses) and are dropped.
+// Partial tiles are summed in LDS in fixed wave order, then handed to
+// rk4_block_lanes with the node data.
+constexpr int kTlThreads = 512, kTlNodes = 4;
+constexpr int kTlJTiles = (kTlNodes * kDout + 15) / 16, kTlTiles = kTlJTiles + 1;
+static_assert(kTlNodes <= kNodesPerBlock, "one RK4 block per workgroup");
+
+template <int S>  // K-steps per lane: H = 32 S
+__global__ void __launch_bounds__(kTlThreads)
+    lat_tail_kernel(int n, const float* __restrict__ hL, const float* __restrict__ G1, const float* __restrict__ W1,
+                    const float* __restrict__ Wo, const float* __restrict__ bo, const float* __restrict__ x,
+                    const float* __restrict__ u, float* __restrict__ y, float* __restrict__ J, FusedRk4 rk,
+                    int input) {
+  constexpr int H = 32 * S, CH = S < 16 ? S : 16;
+  __shared__ float part[kTlThreads / kWave][kTlTiles][256];
+  __shared__ float rs[kTlNodes * kNodeStride + kTlNodes];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, r = lane & 15, kq = lane >> 4;
+  const int node0 = blockIdx.x * kTlNodes, nn = min(kTlNodes, n - node0), rows = nn * kDout;
+  if (t < nn * kNx) rs[(t / kNx) * kNodeStride + t % kNx] = x[(size_t)node0 * kNx + t];
+  if (t < nn * kNu) rs[(t >> 2) * kNodeStride + 13 + (t & 3)] = u[(size_t)node0 * kNu + t];
+  const int kl = wave * (H / 8) + kq * S;  // this lane's k run [kl, kl + S)
+  const float* arow[kTlTiles];
+#pragma unroll
+  for (int rt = 0; rt < kTlJTiles; ++rt)
+    arow[rt] = G1 + ((size_t)node0 * kDout + min(rt * 16 + r, rows - 1)) * H + kl;
+  arow[kTlJTiles] = hL + ((size_t)node0 + min(r, nn - 1)) * H + kl;
+  const float* wy = Wo + (size_t)min(r, kDout - 1) * H + kl;  // columns r >= 6 (and >= 14 of J_D) are dropped
+  const float* wj = W1 + (size_t)kl * kDin + min(r, kDin - 1);
+  f32x4 acc[kTlTiles] = {};
+#pragma unroll
+  for (int c0 = 0; c0 < S; c0 += CH) {
+    float a[kTlTiles][CH], bj[CH], by[CH];
+#pragma unroll
+    for (int i = 0; i < CH; i += 4) {
+#pragma unroll
+      for (int rt = 0; rt < kTlTiles; ++rt) {
+        const float4 v = *reinterpret_cast<const float4*>(arow[rt] + c0 + i);
+        a[rt][i] = v.x, a[rt][i + 1] = v.y, a[rt][i + 2] = v.z, a[rt][i + 3] = v.w;
+      }
+      const float4 w = *reinterpret_cast<const float4*>(wy + c0 + i);
+      by[i] = w.x, by[i + 1] = w.y, by[i + 2] = w.z, by[i + 3] = w.w;
+    }
+#pragma unroll
+    for (int i = 0; i < CH; ++i) bj[i] = wj[(size_t)(c0 + i) * kDin];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+#pragma unroll
+      for (int rt = 0; rt < kTlJTiles; ++rt)
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][i], bj[i], acc[rt], 0, 0, 0);
+      acc[kTlJTiles] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kTlJTiles][i], by[i], acc[kTlJTiles], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int rt = 0; rt < kTlTiles; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wave][rt][(4 * kq + v) * 16 + r] = acc[rt][v];
+  __syncthreads();
+  for (int e = t; e < kTlTiles * 256; e += kTlThreads) {
+    const int rt = e >> 8, el = e & 255, row = el >> 4, col = el & 15;
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < kTlThreads / kWave; ++w) sum += part[w][rt][el];
+    if (rt < kTlJTiles) {
+      const int p = rt * 16 + row;
+      if (p < rows && col < kDin) {
+        J[((size_t)node0 * kDout + p) * kDin + col] = sum;
+        rs[(p / kDout) * kNodeStride + 23 + (p % kDout) * kDin + col] = sum;
+      }
+    } else if (row < nn && col < kDout) {
+      const float yv = sum + bo[col];
+      y[((size_t)node0 + row) * kDout + col] = yv;
+      rs[row * kNodeStride + 17 + col] = yv;
+    }
+  }
+  rk4_block_lanes(rs, reinterpret_cast<int*>(rs + kTlNodes * kNodeStride), nn, node0, t, rk.P, rk.dt, true, rk.xn,
+                  rk.A, rk.B, rk.status, input);
+}
+
+bool lat_tail_fits(const LatNet& net) {
+  const int H = net.H;
+  return net.L >= 2 && (H == 128 || H == 256 || H == 512 || H == 1024) &&
+         reinterpret_cast<uintptr_t>(net.W[net.L]) % 16 == 0;
+}
+
+hipError_t launch_lat_tail(const LatNet& net, int n, const float* act, const float* g, const float* x, const float* u,
+                           float* y, float* J, const FusedRk4& rk, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (!lat_tail_fits(net)) return hipErrorInvalidValue;
+  const int L = net.L, H = net.H;
+  const float* hL = act + (size_t)((L - 1) & 1) * n * H;  // the forward pass's last activations
+  const float* G1 = g + (size_t)6 * n * H;                // the reverse sweep's G_1
+  const dim3 grid((n + kTlNodes - 1) / kTlNodes);
+#define RTN_TAIL(S_)                                                                                              \
+  lat_tail_kernel<S_><<<grid, kTlThreads, 0, st>>>(n, hL, G1, net.W[0], net.W[L], net.b[L], x, u, y, J, rk, net.input)
+  switch (H) {
+    case 128: RTN_TAIL(4); break;
+    case 256: RTN_TAIL(8); break;
+    case 512: RTN_TAIL(16); break;
+    default: RTN_TAIL(32); break;
+  }
+#undef RTN_TAIL
   return hipGetLastError();
 }
 

@@ -77,8 +77,8 @@ struct LatNet {
   const float* b[17];
 };
 // act: [2][n][H] ping-pong activations; sp: [L][n][H] activation derivatives;
-// g: [2][6n][H] ping-pong cotangents; y [n][6]; J [n][6][14] (y, J nullptr: no
-// output layer / no J_D layer).
+// g: [2][6n][H] ping-pong cotangents; y [n][6]; J [n][6][14] (y, J nullptr: the
+// output layer / the J_D layer is left to launch_lat_tail).
 // spp (nullable): act''(a) [L][n][H]; adj (nullable): dy/dh_l [L-1][6n][H] for the
 // hidden layers below the last (dy/dh_L is W_{L+1}).
 hipError_t launch_lat_forward(const LatNet& net, int n, const float* x, const float* u, float* act, float* sp, float* y,
@@ -98,6 +98,12 @@ struct FusedRk4 {
   uint8_t* status;  // nullable
 };
 bool lat_fused_fits(const LatNet& net);
+// Width 128..1024 with L >= 2: J_D (from G_1 = g + 6 n H, left there by
+// launch_lat_reverse with J = nullptr), y (from the last activations in act, left
+// by launch_lat_forward with y = nullptr) and the RK4 step, one launch.
+bool lat_tail_fits(const LatNet& net);
+hipError_t launch_lat_tail(const LatNet& net, int n, const float* act, const float* g, const float* x, const float* u,
+                           float* y, float* J, const FusedRk4& rk, hipStream_t st);
 hipError_t launch_lat_fused(const LatNet& net, int n, const float* x, const float* u, float* y, float* J,
                             hipStream_t st, const FusedRk4* rk4 = nullptr);
 // H_D [n][6][14][14] (+)= T_l^T diag(dy/dh_l (.) act''(a_l)) T_l for layer l (0-based);

@@ -512,15 +512,23 @@ extern "C" rtn_status rtn_linearize(const rtn_model* model, int32_t prec, const 
       return launch_lat_fused(lv, n_nodes, x, u, y, J, q, &rk);
     }
     if (tc.path == 1) {
+      const bool tail = lat_tail_fits(lv);  // J_D, y and RK4 in one launch after the layers
       {
         ProfScope ps("lat_forward", q);
-        if ((e = launch_lat_forward(lv, n_nodes, x, u, lat_act, static_cast<float*>(m->stash), y, q)) != hipSuccess)
+        if ((e = launch_lat_forward(lv, n_nodes, x, u, lat_act, static_cast<float*>(m->stash), tail ? nullptr : y,
+                                    q)) != hipSuccess)
           return e;
       }
       {
         ProfScope ps("lat_reverse", q);
-        if ((e = launch_lat_reverse(lv, n_nodes, static_cast<float*>(m->stash), lat_g, J, q)) != hipSuccess)
+        if ((e = launch_lat_reverse(lv, n_nodes, static_cast<float*>(m->stash), lat_g, tail ? nullptr : J, q)) !=
+            hipSuccess)
           return e;
+      }
+      if (tail) {
+        const FusedRk4 rk{qc, dt, x_next, A, B, status};
+        ProfScope ps("lat_tail_rk4", q);
+        return launch_lat_tail(lv, n_nodes, lat_act, lat_g, x, u, y, J, rk, q);
       }
       ProfScope ps("rk4_lanes", q);
       return launch_rk4_lanes(n_nodes, qc, dt, x, u, y, J, x_next, A, B, status, q, m->input);

@@ -428,20 +428,25 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
       float lmax = 0.f;  // calibration: this lane's max |h|
       // The activation is chosen once per layer, not per value: a branch inside the
       // 16-value loop would serialise each value's exp -> rcp -> product chain.
+      // Row tiles outer, M-tiles inner: a wave's M-tiles of one row are adjacent in
+      // the stash (MTW x 64 bytes), so their stores follow each other and reach
+      // memory as whole lines.
       auto tiles = [&](auto silu) __attribute__((always_inline)) {
+        float bm[C::MTW][16];
 #pragma unroll
-        for (int i = 0; i < C::MTW; ++i) {
-          const int mt = wave * C::MTW + i;
-          float bm[16];
+        for (int i = 0; i < C::MTW; ++i)
 #pragma unroll
-          for (int vi = 0; vi < 16; ++vi) bm[vi] = bias[mt * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3)];
+          for (int vi = 0; vi < 16; ++vi) bm[i][vi] = bias[(wave * C::MTW + i) * 32 + (vi >> 2) * 8 + g * 4 + (vi & 3)];
 #pragma unroll
-          for (int r = 0; r < C::RT; ++r) {
+        for (int r = 0; r < C::RT; ++r) {
+#pragma unroll
+          for (int i = 0; i < C::MTW; ++i) {
+            const int mt = wave * C::MTW + i;
             const int row = row0 + r * 32 + (lane & 31);
             float h[16], sp[16];
 #pragma unroll
             for (int vi = 0; vi < 16; ++vi) {
-              const float a = acc[i][r][vi] * scale + bm[vi];
+              const float a = acc[i][r][vi] * scale + bm[i][vi];
               if constexpr (decltype(silu)::value) {
                 // SiLU h = a s(a), s = logistic; act' = s (1 + a (1 - s)) = s + h (1 - s)
                 const float sg = __builtin_amdgcn_rcpf(1.f + __expf(-a));

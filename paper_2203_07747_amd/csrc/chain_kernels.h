@@ -204,6 +204,10 @@ template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain
         if constexpr (BSrc::kPrefetch) {
 #pragma unroll
           for (int r = 0; r < RT; ++r) b[r] = bn[r];
+          // next step's B reads first, then this step's MFMAs, then the weight loads
+          __builtin_amdgcn_sched_group_barrier(0x100, RT, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, NMT * RT, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, NMT, 0);
         }
         // keep each step's loads where they are issued: PD steps ahead of their use
         __builtin_amdgcn_sched_barrier(0);
@@ -647,8 +651,8 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
     for (int layer = L - 1; layer >= 1; --layer) {  // weights W_{layer+1}^T, stash of h_layer
       f32x16 acc[C::MTW][C::RT];
       sp_fetch(layer - 1, row0);
-      C::template gemm<C::MTW, C::KS_H>(acc, reinterpret_cast<const frag*>(net.rw[layer]), C::MT, C::KS_H,
-                                        wave * C::MTW, 0, blk, lds, lane);
+      C::template gemm<C::MTW, C::KS_H, (C::kOcc > 1 ? 64 : 0)>(acc, reinterpret_cast<const frag*>(net.rw[layer]),
+                                                               C::MT, C::KS_H, wave * C::MTW, 0, blk, lds, lane);
       sp_park();
       __syncthreads();
       const float scale = P == P_FP8 ? net.wscale[layer] * net.gscale[layer] : 1.f;

@@ -16,8 +16,10 @@
 
 namespace rtn {
 
-constexpr int TBM = 64, TBN = 64, TBK = 32;
-
+constexpr int TBM = 64, TBN = 64;
+// K per LDS tile: 128 for bf16 (eight MFMAs per wave between barriers), 32 for
+// fp32 (its fp32 tiles would not fit the static LDS at 128)
+template <int P> constexpr int gemm_tbk() { return P == P_BF16 ? 128 : 32; }
 __device__ inline float from_bits(float v) { return v; }
 __device__ inline float from_bits(uint16_t v) { return bf16_to_f32(v); }
 
@@ -60,18 +62,30 @@ __device__ inline void gemm_store(const GemmArgs& g, int m, int n, float v) {
 // range per grid z-slice; four waves of 32 x 32 (MFMA 32x32x16 bf16 or 32x32x2
 // fp32).  Operands are staged in LDS in the MFMA input type, k-contiguous per row
 // of the tile, loaded with 16-byte global reads along whichever dimension is
-// contiguous.  With one K range the epilogue is applied here, otherwise the fp32
+// contiguous.  The next K tile's global reads are issued before the current
+// tile's products and held in registers, so their latency overlaps the matrix
+// work.  With one K range the epilogue is applied here, otherwise the fp32
 // partial tile is written for gemm_reduce.
 template <int P>
 __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
   using T = typename GemmT<P>::T;
+  constexpr int TBK = gemm_tbk<P>();
   constexpr int PAD = 16 / sizeof(T);  // 16-byte row padding against bank conflicts
+  constexpr int NA = TBM * TBK / 4 / 256, NB = TBN * TBK / 4 / 256;  // float4 groups per thread
   __shared__ __attribute__((aligned(16))) T As[TBM][TBK + PAD];
   __shared__ __attribute__((aligned(16))) T Bs[TBN][TBK + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs in turn, so
+  // workgroup id goes to XCD id % 8; giving each XCD a contiguous eighth of the
+  // (x fastest, then y, then z) tile order keeps the operand rows and columns its
+  // tiles share -- or its whole K split -- in that XCD's L2.
+  const int GX = gridDim.x, GY = gridDim.y, NWG = GX * GY * gridDim.z;
+  int L = blockIdx.x + GX * (blockIdx.y + GY * blockIdx.z);
+  if (NWG % 8 == 0) L = (L % 8) * (NWG / 8) + L / 8;
+  const int bx = L % GX, by = (L / GX) % GY, bz = L / (GX * GY);
+  const int m0 = by * TBM, n0 = bx * TBN;
   const int NN = g.N + ones_col;
-  const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);
+  const int kb = bz * g.kchunk, ke = min(g.K, kb + g.kchunk);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const bool a_vec_k = g.sAk == 1 && (g.sAm & 3) == 0 && ((uintptr_t)g.A & 15) == 0;
   const bool a_vec_m = g.sAm == 1 && (g.sAk & 3) == 0 && ((uintptr_t)g.A & 15) == 0;
@@ -82,45 +96,127 @@ __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
     if (k >= ke || n >= NN) return 0.f;
     return n < g.N ? g.B[(long)k * g.sBk + (long)n * g.sBn] : 1.f;
   };
+  // group e of the A tile: 4 consecutive k of row mm (a_vec_k) or 4 consecutive m at k
+  auto a_load = [&](int k0, int e) -> float4 {
+    if (a_vec_k) {
+      const int mm = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
+      const int m = m0 + mm, k = k0 + kk;
+      if (m < g.M && k + 3 < ke) return *reinterpret_cast<const float4*>(g.A + (long)m * g.sAm + k);
+      return make_float4(a_at(m, k), a_at(m, k + 1), a_at(m, k + 2), a_at(m, k + 3));
+    }
+    const int kk = e / (TBM / 4), mm = (e % (TBM / 4)) * 4;
+    const int m = m0 + mm, k = k0 + kk;
+    if (a_vec_m && m + 3 < g.M && k < ke) return *reinterpret_cast<const float4*>(g.A + m + (long)k * g.sAk);
+    return make_float4(a_at(m, k), a_at(m + 1, k), a_at(m + 2, k), a_at(m + 3, k));
+  };
+  auto a_stage = [&](int e, float4 v) {
+    if (a_vec_k) {
+      const int mm = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
+      stage(&As[mm][kk], v.x); stage(&As[mm][kk + 1], v.y); stage(&As[mm][kk + 2], v.z); stage(&As[mm][kk + 3], v.w);
+    } else {
+      const int kk = e / (TBM / 4), mm = (e % (TBM / 4)) * 4;
+      stage(&As[mm][kk], v.x); stage(&As[mm + 1][kk], v.y); stage(&As[mm + 2][kk], v.z); stage(&As[mm + 3][kk], v.w);
+    }
+  };
+  auto b_load = [&](int k0, int e) -> float4 {
+    if (b_vec_k) {
+      const int nn = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
+      const int n = n0 + nn, k = k0 + kk;
+      if (n < g.N && k + 3 < ke) return *reinterpret_cast<const float4*>(g.B + k + (long)n * g.sBn);
+      return make_float4(b_at(k, n), b_at(k + 1, n), b_at(k + 2, n), b_at(k + 3, n));
+    }
+    const int kk = e / (TBN / 4), nn = (e % (TBN / 4)) * 4;
+    const int n = n0 + nn, k = k0 + kk;
+    if (b_vec_n && n + 3 < g.N && k < ke) return *reinterpret_cast<const float4*>(g.B + (long)k * g.sBk + n);
+    return make_float4(b_at(k, n), b_at(k, n + 1), b_at(k, n + 2), b_at(k, n + 3));
+  };
+  auto b_stage = [&](int e, float4 v) {
+    if (b_vec_k) {
+      const int nn = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
+      stage(&Bs[nn][kk], v.x); stage(&Bs[nn][kk + 1], v.y); stage(&Bs[nn][kk + 2], v.z); stage(&Bs[nn][kk + 3], v.w);
+    } else {
+      const int kk = e / (TBN / 4), nn = (e % (TBN / 4)) * 4;
+      stage(&Bs[nn][kk], v.x); stage(&Bs[nn + 1][kk], v.y); stage(&Bs[nn + 2][kk], v.z); stage(&Bs[nn + 3][kk], v.w);
+    }
+  };
+  // bf16: each thread moves one 8 (k) x 4 (row) block of each operand tile, read as
+  // eight float4 along whichever dimension is contiguous in memory and written to
+  // LDS as four 16-byte runs of 8 consecutive k (the transpose happens in
+  // registers); fp32: groups of 4 as read.
+  auto blk_load = [&](bool vec_k, bool vec_x, int k0, int x0, int nx, auto at, auto ptr, float4 (&r)[8]) {
+    // vec_k: thread = (row xi = tid / 4, k run 32 (tid % 4)); else (row block 4 (tid % 16), k block 8 (tid / 16))
+    if (vec_k) {
+      const int xi = tid >> 2, kq = (tid & 3) * 32, x = x0 + xi;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + kq + 4 * j;
+        r[j] = (x < nx && k + 3 < ke) ? *reinterpret_cast<const float4*>(ptr(x, k))
+                                      : make_float4(at(k, x), at(k + 1, x), at(k + 2, x), at(k + 3, x));
+      }
+    } else {
+      const int xb = (tid & 15) * 4, kb8 = (tid >> 4) * 8, x = x0 + xb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + kb8 + j;
+        r[j] = (vec_x && x + 3 < nx && k < ke) ? *reinterpret_cast<const float4*>(ptr(x, k))
+                                              : make_float4(at(k, x), at(k, x + 1), at(k, x + 2), at(k, x + 3));
+      }
+    }
+  };
+  auto blk_stage = [&](bool vec_k, T (*dst)[TBK + PAD], const float4 (&r)[8]) {
+    if (vec_k) {
+      const int xi = tid >> 2, kq = (tid & 3) * 32;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        i32x4 w;
+        w[0] = (int)pack_bf16x2(r[2 * h].x, r[2 * h].y);
+        w[1] = (int)pack_bf16x2(r[2 * h].z, r[2 * h].w);
+        w[2] = (int)pack_bf16x2(r[2 * h + 1].x, r[2 * h + 1].y);
+        w[3] = (int)pack_bf16x2(r[2 * h + 1].z, r[2 * h + 1].w);
+        *reinterpret_cast<i32x4*>(&dst[xi][kq + 8 * h]) = w;
+      }
+    } else {
+      const int xb = (tid & 15) * 4, kb8 = (tid >> 4) * 8;
+      auto col = [&](int q, int j) { return q == 0 ? r[j].x : q == 1 ? r[j].y : q == 2 ? r[j].z : r[j].w; };
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        i32x4 w;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t] = (int)pack_bf16x2(col(q, 2 * t), col(q, 2 * t + 1));
+        *reinterpret_cast<i32x4*>(&dst[xb + q][kb8]) = w;
+      }
+    }
+  };
+  auto a_ptr = [&](int m, int k) { return g.A + (long)m * g.sAm + (long)k * g.sAk; };
+  auto b_ptr = [&](int n, int k) { return g.B + (long)k * g.sBk + (long)n * g.sBn; };
+  auto a_at2 = [&](int k, int m) { return a_at(m, k); };
+  auto b_at2 = [&](int k, int n) { return b_at(k, n); };
+  float4 ra[8], rb[8];
+  auto load_tiles = [&](int k0) {
+    if constexpr (P == P_BF16) {
+      blk_load(a_vec_k, a_vec_m, k0, m0, g.M, a_at2, a_ptr, ra);
+      blk_load(b_vec_k, b_vec_n, k0, n0, g.N, b_at2, b_ptr, rb);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) ra[j] = a_load(k0, tid + j * 256);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rb[j] = b_load(k0, tid + j * 256);
+    }
+  };
+  load_tiles(kb);
   f32x16 acc = {};
   for (int k0 = kb; k0 < ke; k0 += TBK) {
-    // A tile: 64 x 32 = 512 groups of 4
-    for (int e = tid; e < TBM * TBK / 4; e += 256) {
-      if (a_vec_k) {
-        const int mm = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
-        const int m = m0 + mm, k = k0 + kk;
-        float4 v;
-        if (m < g.M && k + 3 < ke) v = *reinterpret_cast<const float4*>(g.A + (long)m * g.sAm + k);
-        else v = make_float4(a_at(m, k), a_at(m, k + 1), a_at(m, k + 2), a_at(m, k + 3));
-        stage(&As[mm][kk], v.x); stage(&As[mm][kk + 1], v.y); stage(&As[mm][kk + 2], v.z); stage(&As[mm][kk + 3], v.w);
-      } else {
-        const int kk = e / (TBM / 4), mm = (e % (TBM / 4)) * 4;
-        const int m = m0 + mm, k = k0 + kk;
-        float4 v;
-        if (a_vec_m && m + 3 < g.M && k < ke) v = *reinterpret_cast<const float4*>(g.A + m + (long)k * g.sAk);
-        else v = make_float4(a_at(m, k), a_at(m + 1, k), a_at(m + 2, k), a_at(m + 3, k));
-        stage(&As[mm][kk], v.x); stage(&As[mm + 1][kk], v.y); stage(&As[mm + 2][kk], v.z); stage(&As[mm + 3][kk], v.w);
-      }
-    }
-    // B tile: 32 x 64
-    for (int e = tid; e < TBN * TBK / 4; e += 256) {
-      if (b_vec_k) {
-        const int nn = e / (TBK / 4), kk = (e % (TBK / 4)) * 4;
-        const int n = n0 + nn, k = k0 + kk;
-        float4 v;
-        if (n < g.N && k + 3 < ke) v = *reinterpret_cast<const float4*>(g.B + k + (long)n * g.sBn);
-        else v = make_float4(b_at(k, n), b_at(k + 1, n), b_at(k + 2, n), b_at(k + 3, n));
-        stage(&Bs[nn][kk], v.x); stage(&Bs[nn][kk + 1], v.y); stage(&Bs[nn][kk + 2], v.z); stage(&Bs[nn][kk + 3], v.w);
-      } else {
-        const int kk = e / (TBN / 4), nn = (e % (TBN / 4)) * 4;
-        const int n = n0 + nn, k = k0 + kk;
-        float4 v;
-        if (b_vec_n && n + 3 < g.N && k < ke) v = *reinterpret_cast<const float4*>(g.B + (long)k * g.sBk + n);
-        else v = make_float4(b_at(k, n), b_at(k, n + 1), b_at(k, n + 2), b_at(k, n + 3));
-        stage(&Bs[nn][kk], v.x); stage(&Bs[nn + 1][kk], v.y); stage(&Bs[nn + 2][kk], v.z); stage(&Bs[nn + 3][kk], v.w);
-      }
+    if constexpr (P == P_BF16) {
+      blk_stage(a_vec_k, As, ra);
+      blk_stage(b_vec_k, Bs, rb);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) a_stage(tid + j * 256, ra[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) b_stage(tid + j * 256, rb[j]);
     }
     __syncthreads();
+    if (k0 + TBK < ke) load_tiles(k0 + TBK);  // the next tile's reads, in flight during the products
     const int r = lane & 31, h = lane >> 5;
     if constexpr (P == P_BF16) {
 #pragma unroll
@@ -143,7 +239,7 @@ __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
     const int m = m0 + wm + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
     if (m >= g.M || n >= NN) continue;
     if (gridDim.z == 1) gemm_store(g, m, n, gemm_epilogue(g, m, n, acc[i]));
-    else g.part[((long)blockIdx.z * g.M + m) * (g.N + 1) + n] = acc[i];
+    else g.part[((long)bz * g.M + m) * (g.N + 1) + n] = acc[i];
   }
 }
 
@@ -211,8 +307,9 @@ hipError_t launch_gemm(int prec, int M, int N, int K, const float* A, long sAm, 
   const int ones = Cone ? 1 : 0;
   const int splits = (part && K > 0) ? gemm_splits(M, N, K) : 1;
   GemmArgs g{M, N, K, A, sAm, sAk, B, sBk, sBn, C, sCm, Cone, accumulate, gate, gate_is_f32, ldg, part, 0};
-  g.kchunk = K > 0 ? (K + splits - 1) / splits : TBK;
-  g.kchunk = (g.kchunk + TBK - 1) / TBK * TBK;
+  const int tbk = prec == P_BF16 ? gemm_tbk<P_BF16>() : gemm_tbk<P_FP32>();
+  g.kchunk = K > 0 ? (K + splits - 1) / splits : tbk;
+  g.kchunk = (g.kchunk + tbk - 1) / tbk * tbk;
   const int splits_used = K > 0 ? (K + g.kchunk - 1) / g.kchunk : 1;
   dim3 grid((N + ones + TBN - 1) / TBN, (M + TBM - 1) / TBM, splits_used);
   if (prec == P_FP32) gemm_mfma<P_FP32><<<grid, 256, 0, st>>>(g, ones);

@@ -31,7 +31,8 @@ struct Model {
   float* w_out_s = nullptr;  // W_{L+1} with each row in stash order
   bool calibrated = false;
   // packed copies are refreshed lazily, per precision, after the master weights change
-  bool pack_ok[3] = {false, false, false};
+  bool pack_ok[3] = {false, false, false};   // forward copies (and fp8 weight scales)
+  bool rpack_ok[3] = {false, false, false};  // reverse copies
   bool wout_ok = false;
   // workspace (grown on demand)
   void* stash = nullptr;
@@ -70,8 +71,12 @@ struct Model {
   rtn_status alloc(void** p, size_t bytes);
   void release(void* p);
   rtn_status repack(hipStream_t st);  // mark every packed copy stale and refresh all three
-  void invalidate_packs() { pack_ok[0] = pack_ok[1] = pack_ok[2] = wout_ok = false; }
-  rtn_status ensure_packed(int prec, hipStream_t st);
+  void invalidate_packs() {
+    for (int p = 0; p < 3; ++p) pack_ok[p] = rpack_ok[p] = false;
+    wout_ok = false;
+  }
+  // rev = false: only what a forward pass reads (the training forward)
+  rtn_status ensure_packed(int prec, hipStream_t st, bool rev = true);
   rtn_status ensure_workspace(int64_t n, int64_t nrow_train, hipStream_t st);
   NetView view(int prec) const;
   int in_col(int c) const;

@@ -226,26 +226,34 @@ NetView rtn::Model::view(int prec) const {
 
 // Refresh the packed copy of one precision (and, for fp8, the weight scales)
 // from the fp32 master weights if they changed since it was made.
-rtn_status rtn::Model::ensure_packed(int prec, hipStream_t st) {
-  if (!wout_ok) {
+rtn_status rtn::Model::ensure_packed(int prec, hipStream_t st, bool rev) {
+  if (rev && !wout_ok) {
     HIP_TRY(launch_reorder_out(params + w_off[L], H, w_out_s, st));
     wout_ok = true;
   }
-  if (pack_ok[prec]) return RTN_OK;
-  if (prec == P_FP8) {
+  if (!pack_ok[prec]) {
+    if (prec == P_FP8) {
+      for (int l = 0; l <= L; ++l) {
+        int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
+        HIP_TRY(hipMemsetAsync(scales + l, 0, 4, st));
+        HIP_TRY(launch_amax(params + w_off[l], (long)fo * fi, scales + l, st));
+      }
+      HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
+      rpack_ok[prec] = false;  // packed with the scales just replaced
+    }
     for (int l = 0; l <= L; ++l) {
       int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
-      HIP_TRY(hipMemsetAsync(scales + l, 0, 4, st));
-      HIP_TRY(launch_amax(params + w_off[l], (long)fo * fi, scales + l, st));
+      HIP_TRY(launch_pack(prec, params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[prec][l], st));
     }
-    HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
+    pack_ok[prec] = true;
   }
-  for (int l = 0; l <= L; ++l) {
-    int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
-    HIP_TRY(launch_pack(prec, params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[prec][l], st));
-    if (l < L) HIP_TRY(launch_pack(prec, params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[prec][l], st));
+  if (rev && !rpack_ok[prec]) {
+    for (int l = 0; l < L; ++l) {
+      int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
+      HIP_TRY(launch_pack(prec, params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[prec][l], st));
+    }
+    rpack_ok[prec] = true;
   }
-  pack_ok[prec] = true;
   return RTN_OK;
 }
 
@@ -915,7 +923,7 @@ rtn_status rtn::Model::ensure_train_workspace(int64_t batch, hipStream_t st) {
 static rtn_status train_forward(Model* m, int32_t prec, int32_t batch, const float* in, hipStream_t st) {
   rtn_status s = m->ensure_train_workspace(batch, st);
   if (s) return s;
-  if (rtn_status sp = m->ensure_packed(prec, st)) return sp;
+  if (rtn_status sp = m->ensure_packed(prec, st, false)) return sp;
   NetView v = m->view(prec);
   ProfScope ps("mlp_forward_chain(train)", st);
   HIP_TRY(launch_mlp_forward(prec, m->H, v, batch, nullptr, nullptr, in, m->tstash, m->ty, nullptr, st, m->hsave));
@@ -925,8 +933,9 @@ static rtn_status train_forward(Model* m, int32_t prec, int32_t batch, const flo
   return RTN_OK;
 }
 
-// Add dL/dparams of the last forward for upstream gradient dy [batch][6]; din optional.
-static rtn_status train_backward(Model* m, const float* dy, float* din, hipStream_t st) {
+// dL/dparams of the last forward for upstream gradient dy [batch][6], added to the
+// gradient buffer (accumulate) or written over it; din optional.
+static rtn_status train_backward(Model* m, const float* dy, float* din, hipStream_t st, int accumulate = 1) {
   const int B = m->tbatch, H = m->H, L = m->L, prec = m->tprec;
   const int gate_f32 = prec == P_FP32 ? 1 : 0;
   const size_t sb = (size_t)(prec == P_FP32 ? 4 : 2);
@@ -935,7 +944,7 @@ static rtn_status train_backward(Model* m, const float* dy, float* din, hipStrea
   float* part = m->tpart;
   // output layer W_{L+1} (6 x H): dW = dy^T h_L, db = sum dy, delta_L = (dy W) * act'(a_L)
   HIP_TRY(launch_gemm(prec, kDout, H, B, dy, 1, kDout, m->hsave + (size_t)(L - 1) * B * H, H, 1,
-                      m->grad + m->w_off[L], H, m->grad + m->b_off[L], 1, nullptr, 1, 0, part, st));
+                      m->grad + m->w_off[L], H, m->grad + m->b_off[L], accumulate, nullptr, 1, 0, part, st));
   HIP_TRY(launch_gemm(prec, B, H, kDout, dy, kDout, 1, m->params + m->w_off[L], H, 1, m->tdelta[0], H, nullptr, 0,
                       stash + (size_t)(L - 1) * B * H * sb, gate_f32, H, part, st));
   int cur = 0;
@@ -943,8 +952,8 @@ static rtn_status train_backward(Model* m, const float* dy, float* din, hipStrea
     const int fi = l == 0 ? kDin : H;
     const float* hin = l == 0 ? m->tin : m->hsave + (size_t)(l - 1) * B * H;
     const float* d = m->tdelta[cur];
-    HIP_TRY(launch_gemm(prec, H, fi, B, d, 1, H, hin, fi, 1, m->grad + m->w_off[l], fi, m->grad + m->b_off[l], 1,
-                        nullptr, 1, 0, part, st));
+    HIP_TRY(launch_gemm(prec, H, fi, B, d, 1, H, hin, fi, 1, m->grad + m->w_off[l], fi, m->grad + m->b_off[l],
+                        accumulate, nullptr, 1, 0, part, st));
     if (l > 0) {
       HIP_TRY(launch_gemm(prec, B, H, H, d, H, 1, m->params + m->w_off[l], H, 1, m->tdelta[cur ^ 1], H, nullptr, 0,
                           stash + (size_t)(l - 1) * B * H * sb, gate_f32, H, part, st));
@@ -1044,10 +1053,10 @@ rtn_status rtn_train_step(rtn_model* model, int32_t prec, int32_t batch, const f
   Model* m = reinterpret_cast<Model*>(model);
   if (rtn_status sv = full_only(m, "rtn_train_step")) return sv;
   hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipMemsetAsync(m->grad, 0, m->n_params * 4, st));
   if ((s = train_forward(m, prec, batch, in, st))) return s;
   HIP_TRY(launch_mse(batch * kDout, m->ty, target, m->tdy, loss, st));
-  if ((s = train_backward(m, m->tdy, nullptr, st))) return s;
+  // every weight and bias gradient is written by one product (no zeroing needed)
+  if ((s = train_backward(m, m->tdy, nullptr, st, 0))) return s;
   return adam_update(m, lr, beta1, beta2, eps, st);
 }
 

@@ -144,14 +144,20 @@ __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
   // LDS as four 16-byte runs of 8 consecutive k (the transpose happens in
   // registers); fp32: groups of 4 as read.
   auto blk_load = [&](bool vec_k, bool vec_x, int k0, int x0, int nx, auto at, auto ptr, float4 (&r)[8]) {
-    // vec_k: thread = (row xi = tid / 4, k run 32 (tid % 4)); else (row block 4 (tid % 16), k block 8 (tid / 16))
+    // vec_k: four runs of 8 k per thread, run p = jj 256 + tid at row p / 16, k 8 (p % 16), so
+    // that 16 neighbouring lanes read one row's 512 contiguous bytes; else one block of 4
+    // rows (tid % 16) x 8 k (tid / 16)
     if (vec_k) {
-      const int xi = tid >> 2, kq = (tid & 3) * 32, x = x0 + xi;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + kq + 4 * j;
-        r[j] = (x < nx && k + 3 < ke) ? *reinterpret_cast<const float4*>(ptr(x, k))
-                                      : make_float4(at(k, x), at(k + 1, x), at(k + 2, x), at(k + 3, x));
+      for (int jj = 0; jj < 4; ++jj) {
+        const int pr = jj * 256 + tid, x = x0 + (pr >> 4), k = k0 + (pr & 15) * 8;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int kk = k + 4 * hh;
+          r[2 * jj + hh] = (x < nx && kk + 3 < ke)
+                               ? *reinterpret_cast<const float4*>(ptr(x, kk))
+                               : make_float4(at(kk, x), at(kk + 1, x), at(kk + 2, x), at(kk + 3, x));
+        }
       }
     } else {
       const int xb = (tid & 15) * 4, kb8 = (tid >> 4) * 8, x = x0 + xb;
@@ -165,15 +171,15 @@ __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
   };
   auto blk_stage = [&](bool vec_k, T (*dst)[TBK + PAD], const float4 (&r)[8]) {
     if (vec_k) {
-      const int xi = tid >> 2, kq = (tid & 3) * 32;
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int jj = 0; jj < 4; ++jj) {
+        const int pr = jj * 256 + tid;
         i32x4 w;
-        w[0] = (int)pack_bf16x2(r[2 * h].x, r[2 * h].y);
-        w[1] = (int)pack_bf16x2(r[2 * h].z, r[2 * h].w);
-        w[2] = (int)pack_bf16x2(r[2 * h + 1].x, r[2 * h + 1].y);
-        w[3] = (int)pack_bf16x2(r[2 * h + 1].z, r[2 * h + 1].w);
-        *reinterpret_cast<i32x4*>(&dst[xi][kq + 8 * h]) = w;
+        w[0] = (int)pack_bf16x2(r[2 * jj].x, r[2 * jj].y);
+        w[1] = (int)pack_bf16x2(r[2 * jj].z, r[2 * jj].w);
+        w[2] = (int)pack_bf16x2(r[2 * jj + 1].x, r[2 * jj + 1].y);
+        w[3] = (int)pack_bf16x2(r[2 * jj + 1].z, r[2 * jj + 1].w);
+        *reinterpret_cast<i32x4*>(&dst[pr >> 4][(pr & 15) * 8]) = w;
       }
     } else {
       const int xb = (tid & 15) * 4, kb8 = (tid >> 4) * 8;

@@ -147,7 +147,17 @@ __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
     // vec_k: four runs of 8 k per thread, run p = jj 256 + tid at row p / 16, k 8 (p % 16), so
     // that 16 neighbouring lanes read one row's 512 contiguous bytes; else one block of 4
     // rows (tid % 16) x 8 k (tid / 16)
-    if (vec_k) {
+    // a tile wholly inside the operand (uniform over the workgroup) is read without
+    // per-lane bounds checks, so that all sixteen reads are issued back to back
+    const bool inside = x0 + 64 <= nx && k0 + TBK <= ke;
+    if (vec_k && inside) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int pr = jj * 256 + tid, x = x0 + (pr >> 4), k = k0 + (pr & 15) * 8;
+        r[2 * jj] = *reinterpret_cast<const float4*>(ptr(x, k));
+        r[2 * jj + 1] = *reinterpret_cast<const float4*>(ptr(x, k + 4));
+      }
+    } else if (vec_k) {
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const int pr = jj * 256 + tid, x = x0 + (pr >> 4), k = k0 + (pr & 15) * 8;
@@ -159,6 +169,10 @@ __global__ void __launch_bounds__(256) gemm_mfma(GemmArgs g, int ones_col) {
                                : make_float4(at(kk, x), at(kk + 1, x), at(kk + 2, x), at(kk + 3, x));
         }
       }
+    } else if (vec_x && inside) {
+      const int xb = (tid & 15) * 4, kb8 = (tid >> 4) * 8, x = x0 + xb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) r[j] = *reinterpret_cast<const float4*>(ptr(x, k0 + kb8 + j));
     } else {
       const int xb = (tid & 15) * 4, kb8 = (tid >> 4) * 8, x = x0 + xb;
 #pragma unroll

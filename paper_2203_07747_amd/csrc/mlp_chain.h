@@ -29,8 +29,15 @@ template <int P> struct StashT { using type = uint16_t; };
 template <> struct StashT<0> { using type = float; };
 
 int pack_geometry(int prec, int M, int K, int* MT, int* KS);
-hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int trans, const float* scale, void* out,
-                       hipStream_t st);
+// Pack matrices of one precision into MFMA fragment order, in one launch (at
+// most 34): each W fp32 row-major [M or K rows][cols], trans selects W^T.
+struct PackSpec {
+  const float* W;
+  int cols, M, K, trans;
+  const float* scale;
+  void* out;
+};
+hipError_t launch_pack_layers(int prec, int n, const PackSpec* specs, hipStream_t st);
 hipError_t launch_amax(const float* a, long n, float* out, hipStream_t st);
 hipError_t launch_amax_to_scale(float* s, int n, hipStream_t st);
 // Launch configuration of a layer-chain kernel: tile variant (0 = default

@@ -26,25 +26,46 @@ hipError_t launch_reorder_out(const float* W, int H, float* out, hipStream_t st)
 //   out[((s*MT + mt)*64 + lane)*E + j] = A[m][k],  m = 32 mt + lane % 32,
 //   k = slot_feature(s*E + j, lane / 32);  A = W (trans = 0) or W^T (trans = 1),
 //   W fp32 row-major [rows][cols].  Zero outside M x K.
+// One operand matrix of a batched pack (see launch_pack_layers).
+struct PackJob {
+  const float* W;
+  int cols, M, K, trans;
+  const float* scale;
+  void* out;
+  int MT, KS;
+  long begin;  // first element of this job in the launch's element range
+};
+constexpr int kMaxPackJobs = 34;
+struct PackJobs {
+  int n;
+  PackJob j[kMaxPackJobs];
+};
+
 template <int P>
-__global__ void pack_operand(const float* __restrict__ W, int cols, int M, int K, int trans,
-                             const float* __restrict__ scale, typename Mfma<P>::elem* __restrict__ out,
-                             int MT, int KS) {
+__device__ inline void pack_element(const PackJob& q, long idx) {
   constexpr int E = Mfma<P>::E;
-  const long total = (long)MT * KS * kWave * E;
-  const float inv = (P == P_FP8 && scale) ? 1.f / scale[0] : 1.f;
+  const int j = idx % E;
+  const int lane = (idx / E) % kWave;
+  const int mt = (idx / ((long)E * kWave)) % q.MT;
+  const int s = idx / ((long)E * kWave * q.MT);
+  const int m = mt * 32 + (lane & 31);
+  const int k = slot_feature(s * E + j, lane >> 5);
+  float v = 0.f;
+  if (m < q.M && k < q.K) v = q.trans ? q.W[(size_t)k * q.cols + m] : q.W[(size_t)m * q.cols + k];
+  auto* out = static_cast<typename Mfma<P>::elem*>(q.out);
+  if constexpr (P == P_FP32) out[idx] = v;
+  else if constexpr (P == P_BF16) out[idx] = f32_to_bf16_rne(v);
+  else out[idx] = (uint8_t)(f32x2_to_e4m3(v * (q.scale ? 1.f / q.scale[0] : 1.f), 0.f) & 0xffu);
+}
+
+// Every matrix of a model's precision in one launch (one launch per layer costs
+// a few microseconds each after every optimiser step).
+template <int P>
+__global__ void pack_operands(PackJobs jobs, long total) {
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-    const int j = idx % E;
-    const int lane = (idx / E) % kWave;
-    const int mt = (idx / ((long)E * kWave)) % MT;
-    const int s = idx / ((long)E * kWave * MT);
-    const int m = mt * 32 + (lane & 31);
-    const int k = slot_feature(s * E + j, lane >> 5);
-    float v = 0.f;
-    if (m < M && k < K) v = trans ? W[(size_t)k * cols + m] : W[(size_t)m * cols + k];
-    if constexpr (P == P_FP32) out[idx] = v;
-    else if constexpr (P == P_BF16) out[idx] = f32_to_bf16_rne(v);
-    else out[idx] = (uint8_t)(f32x2_to_e4m3(v * inv, 0.f) & 0xffu);
+    int q = 0;
+    while (q + 1 < jobs.n && idx >= jobs.j[q + 1].begin) ++q;
+    pack_element<P>(jobs.j[q], idx - jobs.j[q].begin);
   }
 }
 
@@ -75,18 +96,33 @@ int pack_geometry(int prec, int M, int K, int* MT, int* KS) {
   return *MT * *KS * kWave * E;  // elements
 }
 
-hipError_t launch_pack(int prec, const float* W, int cols, int M, int K, int trans, const float* scale, void* out,
-                       hipStream_t st) {
-  int MT, KS;
-  long total = pack_geometry(prec, M, K, &MT, &KS);
+hipError_t launch_pack_layers(int prec, int n, const PackSpec* specs, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n > kMaxPackJobs) return hipErrorInvalidValue;
+  PackJobs jobs{};
+  jobs.n = n;
+  long total = 0;
+  for (int i = 0; i < n; ++i) {
+    const PackSpec& p = specs[i];
+    PackJob& q = jobs.j[i];
+    q.W = p.W;
+    q.cols = p.cols;
+    q.M = p.M;
+    q.K = p.K;
+    q.trans = p.trans;
+    q.scale = p.scale;
+    q.out = p.out;
+    q.begin = total;
+    total += pack_geometry(prec, p.M, p.K, &q.MT, &q.KS);
+  }
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   if (prec == P_FP32)
-    pack_operand<P_FP32><<<blocks, 256, 0, st>>>(W, cols, M, K, trans, scale, (float*)out, MT, KS);
+    pack_operands<P_FP32><<<blocks, 256, 0, st>>>(jobs, total);
   else if (prec == P_BF16)
-    pack_operand<P_BF16><<<blocks, 256, 0, st>>>(W, cols, M, K, trans, scale, (uint16_t*)out, MT, KS);
+    pack_operands<P_BF16><<<blocks, 256, 0, st>>>(jobs, total);
   else
-    pack_operand<P_FP8><<<blocks, 256, 0, st>>>(W, cols, M, K, trans, scale, (uint8_t*)out, MT, KS);
+    pack_operands<P_FP8><<<blocks, 256, 0, st>>>(jobs, total);
   return hipGetLastError();
 }
 

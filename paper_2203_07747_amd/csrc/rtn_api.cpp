@@ -241,17 +241,21 @@ rtn_status rtn::Model::ensure_packed(int prec, hipStream_t st, bool rev) {
       HIP_TRY(launch_amax_to_scale(scales, L + 1, st));
       rpack_ok[prec] = false;  // packed with the scales just replaced
     }
+    PackSpec fw[kMaxHidden + 1];
     for (int l = 0; l <= L; ++l) {
       int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
-      HIP_TRY(launch_pack(prec, params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[prec][l], st));
+      fw[l] = PackSpec{params + w_off[l], fi, fo, fi, 0, scales + l, packed_fw[prec][l]};
     }
+    HIP_TRY(launch_pack_layers(prec, L + 1, fw, st));
     pack_ok[prec] = true;
   }
   if (rev && !rpack_ok[prec]) {
+    PackSpec rw[kMaxHidden];
     for (int l = 0; l < L; ++l) {
       int fo = (int)layer_fan_out(l), fi = (int)layer_fan_in(l);
-      HIP_TRY(launch_pack(prec, params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[prec][l], st));
+      rw[l] = PackSpec{params + w_off[l], fi, fi, fo, 1, scales + l, packed_rw[prec][l]};
     }
+    HIP_TRY(launch_pack_layers(prec, L, rw, st));
     rpack_ok[prec] = true;
   }
   return RTN_OK;

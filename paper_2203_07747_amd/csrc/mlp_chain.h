@@ -136,7 +136,7 @@ hipError_t launch_rk4_exact_stage(int n, int stage, const QuadConst& q, float dt
 hipError_t launch_lq_rollout(int n_inst, const int* offsets, const float* A, const float* B, const double* c,
                              const double* K, const double* kff, const double* dx0, double* dx, double* du,
                              double* dxN, hipStream_t st);
-constexpr int kBoxWsDoubles = 28;  // per node ADMM state of launch_box_admm
+constexpr int kBoxWsDoubles = 44;  // per node ADMM state of launch_box_admm
 hipError_t launch_box_admm(int n_inst, const int* offsets, const float* A, const float* B, const double* c,
                            const double* QN, const double* Rt, const double* q, const double* r, const double* qN,
                            const double* K, const double* P, const double* dx0, const double* lo, const double* hi,

@@ -275,6 +275,13 @@ hipError_t launch_lq_rollout(int n_inst, const int* offsets, const float* A, con
   return hipGetLastError();
 }
 
+// Lane `lane`'s value of v, in every lane (lane is a constant, v any double).
+__device__ inline double wave_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // ---------------------------------------------------------------------------
 // Input box lo_k <= du_k <= hi_k (the input rows of eq. (3)) by ADMM on the split
 // du = z, z in the box (scaled dual y):
@@ -307,7 +314,7 @@ struct BoxArgs {
   const double* hi;  // [n][4]
   double rho, tol;
   int max_iter;
-  double* ws;        // [n][28]: Quu^-1 (16), z (4), y (4), kff (4)
+  double* ws;        // [n][44]: Quu^-1 (16), z (4), y (4), kff (4), P_{k+1} c_k (13), pad
   double* du;        // [n][4]
   double* dx;        // nullable [n][13]
   double* dxN;       // nullable [n_inst][13]
@@ -320,10 +327,7 @@ constexpr double kBoxRelax = 1.6;
 constexpr int kBoxWs = kBoxWsDoubles;
 
 __global__ void __launch_bounds__(64) box_admm_kernel(BoxArgs a) {
-  __shared__ double sP[NX * NX], sPB[NX * NU], sQuu[NU * NU];
-  __shared__ double sp[NX], sg[NX], sqx[NX], squ[NU], sx[NX], su[NU];
-  __shared__ double sres[2][NU];
-  __shared__ int sdone;
+  __shared__ double sPB[NX * NU], sQuu[NU * NU], sx[NX];
   const int inst = blockIdx.x, t = threadIdx.x;
   const int k0 = a.offsets[inst], k1 = a.offsets[inst + 1];
   auto Pnext = [&](int k) { return k + 1 < k1 ? a.P + (size_t)(k + 1) * NX * NX : a.QN; };
@@ -374,105 +378,118 @@ __global__ void __launch_bounds__(64) box_admm_kernel(BoxArgs a) {
       w[16 + t] = fmin(fmax(0.0, lo), hi);
       w[20 + t] = 0.0;
     }
+    if (t < NX) {  // P_{k+1} c_k, fixed over the iterations
+      double s = 0.0;
+      if (a.c)
+        for (int l = 0; l < NX; ++l) s += Pn[t * NX + l] * a.c[(size_t)k * NX + l];
+      a.ws[(size_t)k * kBoxWs + 28 + t] = s;
+    }
     __syncthreads();
   }
+  // Iterations: one wave and no barriers.  Lanes 0..12 carry the state-sized
+  // vectors (p_k in the backward pass, x_k in the rollout), lanes 16..19 the
+  // input-sized ones (the affine term, z, y); the other lanes compute values that
+  // are never read.  A value one lane computed reaches the others by readlane, and
+  // each lane loads its operands for a node with addresses of its own, all before
+  // the node's first product, so a step waits on no barrier and on one memory
+  // round trip.  Every sum runs in the order of its definition.
+  const bool sl = t < NX, il = t >= 16 && t < 16 + NU;
+  const int ti = il ? t - 16 : 0, ts = sl ? t : 0;
+  const bool hq = a.q != nullptr, hr = a.r != nullptr, hc = a.c != nullptr;
+  const double rho = a.rho;
   int it = 0;
   for (; it < a.max_iter; ++it) {
-    // backward pass of the linear terms
-    if (t < NX) sp[t] = a.qN ? a.qN[(size_t)inst * NX + t] : 0.0;
-    __syncthreads();
+    // backward pass of the linear terms: g = p_{k+1} + P_{k+1} c_k,
+    // (q~, r~) = (q_k + A_k^T g, r_k - rho (z_k - y_k) + B_k^T g),
+    // p_k = q~ + K_k^T r~ (state lanes), d_k = -Quu_k^-1 r~ (input lanes)
+    double p = sl && a.qN ? a.qN[(size_t)inst * NX + ts] : 0.0;
     for (int k = k1 - 1; k >= k0; --k) {
-      const float* Ak = a.A + (size_t)k * NX * NX;
-      const float* Bk = a.B + (size_t)k * NX * NU;
-      const double* Kk = a.K + (size_t)k * NU * NX;
-      double* w = a.ws + (size_t)k * kBoxWs;
-      const double* Pn = Pnext(k);
-      if (t < NX) {
-        double s = sp[t];
-        if (a.c)
-          for (int l = 0; l < NX; ++l) s += Pn[t * NX + l] * a.c[(size_t)k * NX + l];
-        sg[t] = s;
+      const double* w = a.ws + (size_t)k * kBoxWs;
+      // column t of A_k or column i of B_k; column t of K_k or row i of Quu_k^-1
+      const float* c13p = sl ? a.A + (size_t)k * NX * NX + ts : a.B + (size_t)k * NX * NU + ti;
+      const int c13s = sl ? NX : NU;
+      const double* c4p = sl ? a.K + (size_t)k * NU * NX + ts : w + ti * NU;
+      const int c4s = sl ? NX : 1;
+      float c13[NX];
+      double c4[NU];
+#pragma unroll
+      for (int m = 0; m < NX; ++m) c13[m] = c13p[m * c13s];
+#pragma unroll
+      for (int j = 0; j < NU; ++j) c4[j] = c4p[j * c4s];
+      const double qv = hq ? a.q[(size_t)k * NX + ts] : 0.0;
+      const double rv = hr ? a.r[(size_t)k * NU + ti] : 0.0;
+      const double pc = w[28 + ts], zv = w[16 + ti], yv = w[20 + ti];
+      const double g = p + pc;
+      double s1 = sl ? qv : rv - rho * (zv - yv);
+#pragma unroll
+      for (int m = 0; m < NX; ++m) s1 += (double)c13[m] * wave_bcast(g, m);
+      double s2 = sl ? s1 : 0.0;
+      if (sl) {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) s2 += c4[j] * wave_bcast(s1, 16 + j);
+      } else {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) s2 -= c4[j] * wave_bcast(s1, 16 + j);
       }
-      __syncthreads();
-      if (t < NX) {
-        double s = a.q ? a.q[(size_t)k * NX + t] : 0.0;
-        for (int m = 0; m < NX; ++m) s += (double)Ak[m * NX + t] * sg[m];
-        sqx[t] = s;
-      } else if (t >= 16 && t < 16 + NU) {
-        const int i = t - 16;
-        double s = (a.r ? a.r[(size_t)k * NU + i] : 0.0) - a.rho * (w[16 + i] - w[20 + i]);
-        for (int m = 0; m < NX; ++m) s += (double)Bk[m * NU + i] * sg[m];
-        squ[i] = s;
-      }
-      __syncthreads();
-      if (t < NX) {
-        double s = sqx[t];
-        for (int i = 0; i < NU; ++i) s += Kk[i * NX + t] * squ[i];
-        sp[t] = s;
-      } else if (t >= 16 && t < 16 + NU) {
-        const int i = t - 16;
-        double s = 0.0;
-        for (int j = 0; j < NU; ++j) s -= w[i * NU + j] * squ[j];
-        w[24 + i] = s;
-      }
-      __syncthreads();
+      if (il) a.ws[(size_t)k * kBoxWs + 24 + ti] = s2;
+      p = s2;
     }
-    // rollout, projection, dual update
-    if (t < NX) sx[t] = a.dx0[(size_t)inst * NX + t];
+    // rollout with du_k = d_k + K_k x_k, then the z- and y-steps of node k
+    double x = sl ? a.dx0[(size_t)inst * NX + ts] : 0.0;
     double rp = 0.0, rd = 0.0;
-    __syncthreads();
     for (int k = k0; k < k1; ++k) {
-      const float* Ak = a.A + (size_t)k * NX * NX;
-      const float* Bk = a.B + (size_t)k * NX * NU;
-      const double* Kk = a.K + (size_t)k * NU * NX;
       double* w = a.ws + (size_t)k * kBoxWs;
-      if (t >= 16 && t < 16 + NU) {
-        const int i = t - 16;
-        double d = w[24 + i];
-        for (int j = 0; j < NX; ++j) d += Kk[i * NX + j] * sx[j];
-        su[i] = d;
-        const double lo = a.lo[(size_t)k * NU + i], hi = a.hi[(size_t)k * NU + i];
-        const double dr = kBoxRelax * d + (1.0 - kBoxRelax) * w[16 + i];  // over-relaxed du
-        const double zn = fmin(fmax(dr + w[20 + i], lo), hi);
+      const float* Ar = a.A + (size_t)k * NX * NX + ts * NX;   // row t of A_k
+      const float* Br = a.B + (size_t)k * NX * NU + ts * NU;   // row t of B_k
+      const double* Kr = a.K + (size_t)k * NU * NX + ti * NX;  // row i of K_k
+      double c13[NX];
+      float b4[NU];
+      if (sl) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) c13[j] = (double)Ar[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) c13[j] = Kr[j];
+      }
+#pragma unroll
+      for (int j = 0; j < NU; ++j) b4[j] = Br[j];
+      const double cv = hc ? a.c[(size_t)k * NX + ts] : 0.0;
+      const double dv = w[24 + ti], zv = w[16 + ti], yv = w[20 + ti];
+      const double lo = a.lo[(size_t)k * NU + ti], hi = a.hi[(size_t)k * NU + ti];
+      double s3 = sl ? cv : dv;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) s3 += c13[j] * wave_bcast(x, j);
+      if (il) {
+        const double d = s3;
+        const double dr = kBoxRelax * d + (1.0 - kBoxRelax) * zv;  // over-relaxed du
+        const double zn = fmin(fmax(dr + yv, lo), hi);
         rp = fmax(rp, fabs(d - zn));
-        rd = fmax(rd, a.rho * fabs(zn - w[16 + i]));
-        w[20 + i] += dr - zn;
-        w[16 + i] = zn;
+        rd = fmax(rd, rho * fabs(zn - zv));
+        w[20 + ti] = yv + (dr - zn);
+        w[16 + ti] = zn;
       }
-      __syncthreads();
-      double nx = 0.0;
-      if (t < NX) {
-        nx = a.c ? a.c[(size_t)k * NX + t] : 0.0;
-        for (int j = 0; j < NX; ++j) nx += (double)Ak[t * NX + j] * sx[j];
-        for (int j = 0; j < NU; ++j) nx += (double)Bk[t * NU + j] * su[j];
-      }
-      __syncthreads();
-      if (t < NX) sx[t] = nx;
-      __syncthreads();
+      double s4 = s3;
+#pragma unroll
+      for (int j = 0; j < NU; ++j) s4 += (double)b4[j] * wave_bcast(s3, 16 + j);
+      x = s4;
     }
-    if (t >= 16 && t < 16 + NU) {
-      sres[0][t - 16] = rp;
-      sres[1][t - 16] = rd;
+    double mp = 0.0, md = 0.0;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      mp = fmax(mp, wave_bcast(rp, 16 + j));
+      md = fmax(md, wave_bcast(rd, 16 + j));
     }
-    __syncthreads();
-    if (t == 0) {
-      double mp = 0.0, md = 0.0;
-      for (int i = 0; i < NU; ++i) {
-        mp = fmax(mp, sres[0][i]);
-        md = fmax(md, sres[1][i]);
-      }
-      sdone = (mp < a.tol && md < a.tol) ? 1 : 0;
-      if (a.resid) {
-        a.resid[(size_t)inst * 2] = mp;
-        a.resid[(size_t)inst * 2 + 1] = md;
-      }
+    if (t == 0 && a.resid) {
+      a.resid[(size_t)inst * 2] = mp;
+      a.resid[(size_t)inst * 2 + 1] = md;
     }
-    __syncthreads();
-    if (sdone) {
+    if (mp < a.tol && md < a.tol) {
       ++it;
       break;
     }
   }
+  // z was written by the input lanes; the rollout below reads it in the state lanes
+  __syncthreads();
   // outputs: the box-feasible inputs z and the states they produce
   if (t < NX) sx[t] = a.dx0[(size_t)inst * NX + t];
   __syncthreads();

@@ -265,6 +265,14 @@ def extras(torch, rtn, lin_out, off, stream):
         ms_py, _ = time_steps(torch, f, 200, 20, stream, warm_s=0.05)
         call = rtn.LinearizeCall(xt, ut, m, "fp32", cfg.dt, offsets=o, stream=stream)
         ms, wall = time_steps(torch, call, 200, 20, stream, warm_s=0.05)
+        # one call at a time, each waited for (a real-time loop): host wall time per call
+        iso = []
+        for _ in range(220):
+            t0 = time.perf_counter()
+            call()
+            stream.synchronize()
+            iso.append(time.perf_counter() - t0)
+        iso_us = float(np.median(iso[20:])) * 1e6
         # one control iteration: the linearisation and the fp64 Riccati solve of its A_k, B_k
         lo = call()
         ric = rtn.RiccatiCall(lo["A"], lo["B"], np.eye(13), 0.1 * np.eye(4), np.eye(13), offsets=o, stream=stream)
@@ -280,6 +288,7 @@ def extras(torch, rtn, lin_out, off, stream):
         kern = rtn.profile_collect()
         rtn.profile_enable(False)
         res[f"latency_{key}"] = {"workload": cfg.name, "us_per_call": ms * 1e3, "host_us_per_call": wall * 1e3,
+                                 "us_per_call_isolated_median": iso_us,
                                  "us_per_call_unprepared_python_call": ms_py * 1e3,
                                  "us_per_iteration_with_riccati_fp64": ms_it * 1e3,  # both calls prepared
                                  "tile_choice": tile_choice(rtn, "fp32", cfg.width, cfg.n_hidden, x.shape[0]),

@@ -713,13 +713,15 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
 
     // J_D = G_1 W_1: one M-tile (14 used), K split over the waves
     {
-      if (blk + (int)gridDim.x < nblocks) sp_fetch(L - 1, (blk + gridDim.x) * R);
       f32x16 acc[1][C::RT];
       const int s0 = wave * C::SPLIT;
       if (s0 < C::KS_H)
         C::template gemm<1, C::SPLIT>(acc, reinterpret_cast<const frag*>(net.rw[0]), 1, C::KS_H, 0, s0, 0, lds, lane);
       else
         for (int r = 0; r < C::RT; ++r) acc[0][r] = f32x16{};
+      // the next block's first rows: requested after the J_D product's weight loads,
+      // which would otherwise return only after these (loads complete in order)
+      if (blk + (int)gridDim.x < nblocks) sp_fetch(L - 1, (blk + gridDim.x) * R);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < C::RT; ++r)

@@ -169,6 +169,42 @@ def test_box_constrained_lq_matches_exact_minimiser(torch):
     assert active > 0
 
 
+def test_box_lq_single_node_and_long_horizons(torch):
+    """The box ADMM steps through an instance one node at a time in one wave, so horizons
+    of 1, 2, 37 and 120 nodes in one batch (most inputs on a bound) must all reach the
+    exact box-QP minimiser; the random A_k are kept near 0.97 I so the 120-node
+    condensed QP stays well conditioned (cond < 1e4)."""
+    import paper_2203_07747_amd as rtn
+    hz = np.array([1, 2, 37, 120])
+    off = offsets_from_horizons(hz)
+    n, ni = int(off[-1]), len(hz)
+    rng = np.random.default_rng(41)
+    A = (0.97 * np.eye(13) + 0.03 * rng.normal(size=(n, 13, 13))).astype(np.float32)
+    B = (0.2 * rng.normal(size=(n, 13, 4))).astype(np.float32)
+    c = rng.normal(size=(n, 13)) * 0.1
+    q = rng.normal(size=(n, 13)); r = rng.normal(size=(n, 4)); qN = rng.normal(size=(ni, 13))
+    dx0 = 2 * rng.normal(size=(ni, 13))
+    lo = -rng.uniform(0.1, 0.4, size=(n, 4)); hi = rng.uniform(0.1, 0.4, size=(n, 4))
+    Q = np.eye(13); R = 0.1 * np.eye(4); QN = np.eye(13)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    print(f"[gpu] riccati_box horizons {hz.tolist()}", flush=True)
+    out = rtn.riccati_box(dev(A), dev(B), Q, R, QN, dev(dx0), dev(lo), dev(hi), offsets=off, c=dev(c), q=dev(q),
+                          r=dev(r), qN=dev(qN), rho=1.0, max_iter=20000, tol=1e-11)
+    torch.cuda.synchronize()
+    du, dx, dxN = out["du"].cpu().numpy(), out["dx"].cpu().numpy(), out["dxN"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    print(f"  iterations {iters.tolist()}", flush=True)
+    assert np.all(iters < 20000)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    for i in range(ni):
+        a, b = int(off[i]), int(off[i + 1])
+        du_ref, dx_ref = box_lq(A64[a:b], B64[a:b], Q, R, QN, dx0[i], lo[a:b], hi[a:b], c[a:b], q[a:b], r[a:b],
+                                qN[i])
+        np.testing.assert_allclose(du[a:b], du_ref, atol=1e-8)
+        np.testing.assert_allclose(dx[a:b], dx_ref[:-1], atol=1e-7)
+        np.testing.assert_allclose(dxN[i], dx_ref[-1], atol=1e-7)
+
+
 def test_box_lq_with_inactive_box_equals_unconstrained_step(torch):
     import paper_2203_07747_amd as rtn
     hz = sample_horizons(9, 1, 10, seed=9)

@@ -62,6 +62,9 @@ template <int P, int H, bool REV> struct ChainShapeDefault {
 //   V = 4: bf16/fp8 width 512: 128 rows over 8 waves (two per SIMD, each 2
 //          M-tiles x 4 row tiles), one workgroup per CU: half the weight
 //          traffic of two 64-row workgroups, and a 4-step weight ring.
+//   V = 5: reverse, bf16/fp8 width 512: variant 4 with 64 rows (2 row tiles per
+//          wave).  Not a choice of its own: variant 4 runs its last, partly
+//          filled round of blocks in this shape on all workgroups.
 // OCC is the number of waves per SIMD the register budget is sized for.
 template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
   using D = ChainShapeDefault<P, H, REV>;
@@ -73,15 +76,16 @@ template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
                                  (H / 32 / 4) * 2 * 16 <= 128;
   static constexpr int R2 = FITS64 ? 64 : 32;
   static constexpr int NW =
-      V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : V == 4 ? 8 : 4;
+      V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : (V == 4 || V == 5) ? 8 : 4;
   static constexpr int R =
-      V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : V == 2 ? R2 : 128;
+      V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : V == 2 ? R2 : V == 5 ? 64 : 128;
   static constexpr int OCC = V == 2 ? 2 : (NW <= 4 ? 1 : 2);
   static constexpr bool VALID =
       V == 0 || (V == 1 && H >= 512 && R >= 32) ||
       (V == 2 && H >= 512 && R * H * ESZ + (REV ? 7 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
        (H / 32 / 4) * (R / 32) * 16 <= 128) ||
-      (V == 3 && REV && H == 512 && P != P_FP32) || (V == 4 && H == 512 && P != P_FP32);
+      (V == 3 && REV && H == 512 && P != P_FP32) || (V == 4 && H == 512 && P != P_FP32) ||
+      (V == 5 && REV && H == 512 && P != P_FP32);
 };
 
 // OCC: waves per SIMD the kernel is built for (1: the whole register file and,
@@ -523,7 +527,7 @@ template <int P, int H, int V>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, true, V>::NW * kWave),
                                amdgpu_waves_per_eu(ChainShape<P, H, true, V>::OCC)))
 mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict__ stash,
-                  float* __restrict__ J, float* __restrict__ amax) {
+                  float* __restrict__ J, float* __restrict__ amax, int row_begin, int row_end) {
   constexpr int NW = ChainShape<P, H, true, V>::NW, R = ChainShape<P, H, true, V>::R;
   using C = Chain<P, H, R, NW, ChainShape<P, H, true, V>::OCC>;
   using elem = typename C::elem;
@@ -541,8 +545,9 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
   const int wo_stride = C::WO_IN_LDS ? C::WOS : H;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
-  const int nrows = 6 * n;
-  const int nblocks = (nrows + R - 1) / R;
+  // rows [row_begin, row_end) of the 6 n, in blocks of R from row_begin
+  const int nrows = row_end;
+  const int nblocks = (row_end - row_begin + R - 1) / R;
   const int L = net.L;
   const size_t layer_stride = (size_t)n * H;
 
@@ -574,9 +579,9 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
       reinterpret_cast<float4*>(wo_lds + j * C::WOS)[c] = reinterpret_cast<const float4*>(net.w_out_s)[i];
     }
   }
-  if (blockIdx.x < nblocks) sp_fetch(L - 1, blockIdx.x * R);
+  if (blockIdx.x < nblocks) sp_fetch(L - 1, row_begin + blockIdx.x * R);
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-    const int row0 = blk * R;
+    const int row0 = row_begin + blk * R;
     const int node0 = row0 / 6;
     sp_park();
     __syncthreads();
@@ -721,7 +726,7 @@ mlp_reverse_chain(NetView net, int n, const typename StashT<P>::type* __restrict
         for (int r = 0; r < C::RT; ++r) acc[0][r] = f32x16{};
       // the next block's first rows: requested after the J_D product's weight loads,
       // which would otherwise return only after these (loads complete in order)
-      if (blk + (int)gridDim.x < nblocks) sp_fetch(L - 1, (blk + gridDim.x) * R);
+      if (blk + (int)gridDim.x < nblocks) sp_fetch(L - 1, row_begin + (blk + gridDim.x) * R);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < C::RT; ++r)
@@ -774,11 +779,28 @@ hipError_t chain_reverse_v(const ChainCfg& cfg, const NetView& net, int n, const
   if constexpr (!Sh::VALID) {
     return hipErrorInvalidValue;
   } else {
-    const int grid = chain_grid((6 * n + Sh::R - 1) / Sh::R, cfg);
+    using S = typename StashT<P>::type;
+    const int nrows = 6 * n, nblk = (nrows + Sh::R - 1) / Sh::R;
+    const int grid = chain_grid(nblk, cfg);
     if (grid <= 0) return hipSuccess;
-    mlp_reverse_chain<P, H, V><<<grid, Sh::NW * kWave, 0, st>>>(net, n, (const typename StashT<P>::type*)stash, J,
-                                                                amax);
-    return hipGetLastError();
+    int split = nrows;  // rows of this shape's launch; the rest go to the tail launch
+    if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) {
+      // a last round of 128-row blocks that would keep at most half of the
+      // workgroups busy runs instead as 64-row blocks spread over all of them
+      const int rem = nblk % grid;
+      if (nblk > grid && rem > 0 && 2 * rem <= grid) split = (nblk - rem) * Sh::R;
+    }
+    mlp_reverse_chain<P, H, V><<<grid, Sh::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, 0, split);
+    hipError_t e = hipGetLastError();
+    if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) {
+      if (e == hipSuccess && split < nrows) {
+        using S5 = ChainShape<P, H, true, 5>;
+        const int nb5 = (nrows - split + S5::R - 1) / S5::R;
+        mlp_reverse_chain<P, H, 5><<<nb5, S5::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, split, nrows);
+        e = hipGetLastError();
+      }
+    }
+    return e;
   }
 }
 

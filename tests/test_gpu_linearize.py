@@ -236,12 +236,13 @@ def test_bf16_matches_emulation_and_oracle(torch):
 
 # (path, forward variant, forward workgroups, reverse variant, reverse workgroups) the
 # autotuner keeps for 14-5x512-6 bf16 at 122,452 nodes on MI355X (one round of 256
-# resident 128-row workgroups forward; one 128-row workgroup per block reverse), and
-# the default shapes
-C3_CHOICES = [(0, 4, 256, 4, 5740), (0, 0, 0, 0, 0)]
+# resident 128-row workgroups forward; one 128-row workgroup per block reverse, or
+# 256 / 512 persistent ones, whose last partly filled round of the 5,740 blocks runs
+# as 64-row blocks in a second launch), and the default shapes
+C3_CHOICES = [(0, 4, 256, 4, 5740), (0, 4, 256, 4, 256), (0, 0, 0, 0, 0)]
 
 
-@pytest.mark.parametrize("choice", C3_CHOICES, ids=["bench-shape", "default-shape"])
+@pytest.mark.parametrize("choice", C3_CHOICES, ids=["bench-shape", "bench-shape-persistent", "default-shape"])
 def test_c3_full_size_sampled(torch, choice):
     """The benchmarked workload (4096 instances, ragged horizons, 14-5x512-6 bf16) at full size
     in the launch configuration the benchmark times; the oracle checks a seeded sample of
@@ -403,7 +404,7 @@ def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
         for choice in [(0, 0, 0, 0, 0), (0, 1, 0, 1, 0), (0, 1, 1, 1, 1), (0, 0, 3, 1, 7), (0, 1, 5, 0, 2),
                        (0, 0, 10000, 0, 10000), (0, 2, 0, 2, 0), (0, 2, 3, 2, 5), (0, 2, 10000, 2, 1),
                        (0, 0, 0, 3, 0), (0, 2, 0, 3, 3), (0, 2, 0, 4, 0), (0, 0, 0, 4, 3), (0, 4, 0, 4, 0),
-                       (0, 4, 5, 0, 0)]:
+                       (0, 4, 5, 0, 0), (0, 0, 0, 4, 8), (0, 4, 0, 4, 16)]:
             if (choice[3] in (3, 4) or choice[1] == 4) and (prec == "fp32" or H != 512):
                 continue
             print(f"[gpu] tile choice {choice} prec={prec} H={H} L={L} n={n}", flush=True)

@@ -39,9 +39,11 @@ def flops_per_node(L: int, H: int, d_in: int = 14, d_out: int = 6):
 
 
 def measured_traffic(config_key: str, kernel_prefix: str, nodes: int):
-    """HBM bytes of a kernel launch over `nodes` nodes, scaled from the committed counter
-    summary (profiles/linearize_<config>_*_hbm_traffic.json, bytes per node), only while
-    every kernel source the counters were taken on is unchanged; else None."""
+    """HBM bytes of one call's launches of a kernel (every instance whose name starts with
+    kernel_prefix: the reverse chain's tail runs as a second launch) over `nodes` nodes,
+    scaled from the committed counter summary (profiles/linearize_<config>_*_hbm_traffic.json,
+    bytes per node), only while every kernel source the counters were taken on is unchanged;
+    else None."""
     import glob
     import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", f"linearize_{config_key}_*_hbm_traffic.json")):
@@ -50,9 +52,9 @@ def measured_traffic(config_key: str, kernel_prefix: str, nodes: int):
             f = os.path.join(ROOT, src)
             if not os.path.exists(f) or hashlib.sha256(open(f, "rb").read()).hexdigest() != digest:
                 return None
-        for k, v in rec["per_launch"].items():
-            if k.split("::")[-1].startswith(kernel_prefix):
-                return (v["read_bytes"] + v["write_bytes"]) / rec["nodes_per_launch"] * nodes
+        hits = [v for k, v in rec["per_launch"].items() if k.split("::")[-1].startswith(kernel_prefix)]
+        if hits:
+            return sum(v["read_bytes"] + v["write_bytes"] for v in hits) / rec["nodes_per_launch"] * nodes
     return None
 
 

@@ -784,13 +784,19 @@ hipError_t chain_reverse_v(const ChainCfg& cfg, const NetView& net, int n, const
     const int grid = chain_grid(nblk, cfg);
     if (grid <= 0) return hipSuccess;
     int split = nrows;  // rows of this shape's launch; the rest go to the tail launch
+    int grid_main = grid;
     if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) {
       // a last round of 128-row blocks that would keep at most half of the
-      // workgroups busy runs instead as 64-row blocks spread over all of them
-      const int rem = nblk % grid;
-      if (nblk > grid && rem > 0 && 2 * rem <= grid) split = (nblk - rem) * Sh::R;
+      // resident workgroups busy (one per CU in this shape) runs instead as
+      // 64-row blocks spread over all of them
+      const int slots = grid < num_cu() ? grid : num_cu();
+      const int rem = nblk % slots;
+      if (nblk > slots && rem > 0 && 2 * rem <= slots) {
+        split = (nblk - rem) * Sh::R;
+        grid_main = chain_grid(nblk - rem, cfg);
+      }
     }
-    mlp_reverse_chain<P, H, V><<<grid, Sh::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, 0, split);
+    mlp_reverse_chain<P, H, V><<<grid_main, Sh::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, 0, split);
     hipError_t e = hipGetLastError();
     if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) {
       if (e == hipSuccess && split < nrows) {

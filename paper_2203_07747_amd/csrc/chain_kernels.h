@@ -62,9 +62,9 @@ template <int P, int H, bool REV> struct ChainShapeDefault {
 //   V = 4: bf16/fp8 width 512: 128 rows over 8 waves (two per SIMD, each 2
 //          M-tiles x 4 row tiles), one workgroup per CU: half the weight
 //          traffic of two 64-row workgroups, and a 4-step weight ring.
-//   V = 5: reverse, bf16/fp8 width 512: variant 4 with 64 rows (2 row tiles per
-//          wave).  Not a choice of its own: variant 4 runs its last, partly
-//          filled round of blocks in this shape on all workgroups.
+//   V = 5, 6: bf16/fp8 width 512: variant 4 with 64 or 96 rows (2 or 3 row tiles
+//          per wave).  Not choices of their own: variant 4 runs its last, partly
+//          filled round of blocks in one of these shapes on all workgroups.
 // OCC is the number of waves per SIMD the register budget is sized for.
 template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
   using D = ChainShapeDefault<P, H, REV>;
@@ -76,16 +76,20 @@ template <int P, int H, bool REV = true, int V = 0> struct ChainShape {
                                  (H / 32 / 4) * 2 * 16 <= 128;
   static constexpr int R2 = FITS64 ? 64 : 32;
   static constexpr int NW =
-      V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : (V == 4 || V == 5) ? 8 : 4;
-  static constexpr int R =
-      V == 0 ? D::R : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2)) : V == 2 ? R2 : V == 5 ? 64 : 128;
+      V == 0 ? D::NW : V == 1 ? (D::ONE_PER_SIMD ? 8 : (ALT_ONE ? 4 : D::NW)) : V >= 4 ? 8 : 4;
+  static constexpr int R = V == 0   ? D::R
+                           : V == 1 ? (D::ONE_PER_SIMD ? 64 : (ALT_ONE ? 96 : D::R / 2))
+                           : V == 2 ? R2
+                           : V == 5 ? 64
+                           : V == 6 ? 96
+                                    : 128;
   static constexpr int OCC = V == 2 ? 2 : (NW <= 4 ? 1 : 2);
   static constexpr bool VALID =
       V == 0 || (V == 1 && H >= 512 && R >= 32) ||
       (V == 2 && H >= 512 && R * H * ESZ + (REV ? 7 * (H + 16 / SPE) * SPE : 0) <= 80 * 1024 &&
        (H / 32 / 4) * (R / 32) * 16 <= 128) ||
       (V == 3 && REV && H == 512 && P != P_FP32) || (V == 4 && H == 512 && P != P_FP32) ||
-      (V == 5 && REV && H == 512 && P != P_FP32);
+      ((V == 5 || V == 6) && H == 512 && P != P_FP32);
 };
 
 // OCC: waves per SIMD the kernel is built for (1: the whole register file and,
@@ -105,8 +109,10 @@ template <int P, int H, int R, int NW, int OCC = (NW <= 4 ? 1 : 2)> struct Chain
   static constexpr int B_BYTES = R * H * (int)sizeof(elem);
   static constexpr int PART_BYTES = NW * R * 16 * 4;
   static constexpr int LDS_BYTES = B_BYTES > PART_BYTES ? B_BYTES : PART_BYTES;
-  // reverse sweep: the activation derivatives of the nodes a row block touches
-  static constexpr int SP_NODES = R % 6 == 0 ? R / 6 : R / 6 + 2;
+  // reverse sweep: the activation derivatives of the nodes a row block touches;
+  // a block may start at any row (the tail launches), so R rows from offset 5
+  // within a node reach floor((R + 4) / 6) + 1 nodes
+  static constexpr int SP_NODES = (R + 4) / 6 + 1;
   static constexpr int SP_ELEM = P == P_FP32 ? 4 : 2;
   static constexpr int SPS = H + 16 / SP_ELEM;  // LDS row stride (elements): 16-byte pad against bank conflicts
   static constexpr int SP_BYTES = SP_NODES * SPS * SP_ELEM;
@@ -381,7 +387,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, ChainShape<P, H, f
                                amdgpu_waves_per_eu(ChainShape<P, H, false, V>::OCC)))
 mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* __restrict__ u,
                   const float* __restrict__ zin, typename StashT<P>::type* __restrict__ stash,
-                  float* __restrict__ y, float* __restrict__ amax, float* __restrict__ hsave) {
+                  float* __restrict__ y, float* __restrict__ amax, float* __restrict__ hsave, int row_begin,
+                  int row_end) {
   constexpr int NW = ChainShape<P, H, false, V>::NW, R = ChainShape<P, H, false, V>::R;
   using C = Chain<P, H, R, NW, ChainShape<P, H, false, V>::OCC>;
   using elem = typename C::elem;
@@ -392,10 +399,11 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
   float* part = reinterpret_cast<float*>(smem);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
-  const int nblocks = (n + R - 1) / R;
+  // rows (nodes) [row_begin, row_end) of the n, in blocks of R from row_begin
+  const int nblocks = (row_end - row_begin + R - 1) / R;
   const float* dq = net.wscale;  // fp8 only
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-    const int row0 = blk * R;
+    const int row0 = row_begin + blk * R;
     // z_0 (the network input features) into operand slots of K1 features
     for (int it = tid; it < C::RT * C::KS_1 * kWave; it += NW * kWave) {
       const int l = it % kWave, s = (it / kWave) % C::KS_1, rt = it / (kWave * C::KS_1);
@@ -405,7 +413,7 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
       for (int j = 0; j < C::E; ++j) {
         const int k = slot_feature(s * C::E + j, gg);
         float z = 0.f;
-        if (row < n && k < kDin)
+        if (row < row_end && k < kDin)
           z = zin ? zin[(size_t)row * kDin + k] : net_feature(x + (size_t)row * kNx, u + (size_t)row * kNu, k, net.input);
         v[j] = z;
       }
@@ -465,12 +473,12 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
                 sp[vi] = 1.f;
               }
             }
-            if (amax && row < n) {
+            if (amax && row < row_end) {
 #pragma unroll
               for (int vi = 0; vi < 16; ++vi) lmax = fmaxf(lmax, fabsf(h[vi]));
             }
-            if (row < n) store16<S>(st + (size_t)row * H + mt * 32 + g * 16, sp);
-            if (hsave && row < n) {  // training: h_l in natural feature order
+            if (row < row_end) store16<S>(st + (size_t)row * H + mt * 32 + g * 16, sp);
+            if (hsave && row < row_end) {  // training: h_l in natural feature order
               float* hd = hsave + ((size_t)layer * n + row) * H + mt * 32 + g * 4;
 #pragma unroll
               for (int q4 = 0; q4 < 4; ++q4)
@@ -508,7 +516,7 @@ mlp_forward_chain(NetView net, int n, const float* __restrict__ x, const float* 
         const int rr = t / kDout, j = t % kDout, row = row0 + rr;
         float s = 0.f;
         for (int w = 0; w < NW; ++w) s += part[(w * R + rr) * 8 + j];
-        if (row < n) y[(size_t)row * kDout + j] = s * scale + net.bias[net.L][j];
+        if (row < row_end) y[(size_t)row * kDout + j] = s * scale + net.bias[net.L][j];
       }
       __syncthreads();
     }
@@ -757,6 +765,23 @@ inline int chain_grid(int blocks, const ChainCfg& cfg) {
   return blocks < want ? blocks : want;
 }
 
+// Variant 4 (128-row blocks, one workgroup per CU) with a last round of blocks that
+// would keep at most three quarters of the resident workgroups busy: that round's
+// rows go to a second launch of 64-row (up to half busy) or 96-row blocks, which
+// spreads them over all CUs.  rows: rows of the launch; grid: workgroups kept.
+struct TailPlan {
+  int split;      // rows of the 128-row launch; rows [split, rows) go to the tail
+  int tail_rows;  // 64 or 96 rows per tail block (0: no tail)
+  int grid_main;  // workgroups of the 128-row launch
+};
+inline TailPlan tail_plan(int rows, int grid, const ChainCfg& cfg) {
+  const int nblk = (rows + 127) / 128;
+  const int slots = grid < num_cu() ? grid : num_cu();
+  const int rem = slots > 0 ? nblk % slots : 0;
+  if (nblk <= slots || rem == 0 || 4 * rem > 3 * slots) return {rows, 0, grid};
+  return {(nblk - rem) * 128, 2 * rem <= slots ? 64 : 96, chain_grid(nblk - rem, cfg)};
+}
+
 template <int P, int H, int V>
 hipError_t chain_forward_v(const ChainCfg& cfg, const NetView& net, int n, const float* x, const float* u,
                            const float* zin, void* stash, float* y, float* amax, float* hsave, hipStream_t st) {
@@ -764,11 +789,26 @@ hipError_t chain_forward_v(const ChainCfg& cfg, const NetView& net, int n, const
   if constexpr (!Sh::VALID) {
     return hipErrorInvalidValue;
   } else {
+    using S = typename StashT<P>::type;
     const int grid = chain_grid((n + Sh::R - 1) / Sh::R, cfg);
     if (grid <= 0) return hipSuccess;
-    mlp_forward_chain<P, H, V><<<grid, Sh::NW * kWave, 0, st>>>(net, n, x, u, zin,
-                                                                (typename StashT<P>::type*)stash, y, amax, hsave);
-    return hipGetLastError();
+    TailPlan tp{n, 0, grid};
+    if constexpr (V == 4 && ChainShape<P, H, false, 5>::VALID) tp = tail_plan(n, grid, cfg);
+    mlp_forward_chain<P, H, V><<<tp.grid_main, Sh::NW * kWave, 0, st>>>(net, n, x, u, zin, (S*)stash, y, amax,
+                                                                        hsave, 0, tp.split);
+    hipError_t e = hipGetLastError();
+    if constexpr (V == 4 && ChainShape<P, H, false, 5>::VALID) {
+      if (e == hipSuccess && tp.tail_rows == 64) {
+        mlp_forward_chain<P, H, 5><<<(n - tp.split + 63) / 64, ChainShape<P, H, false, 5>::NW * kWave, 0, st>>>(
+            net, n, x, u, zin, (S*)stash, y, amax, hsave, tp.split, n);
+        e = hipGetLastError();
+      } else if (e == hipSuccess && tp.tail_rows == 96) {
+        mlp_forward_chain<P, H, 6><<<(n - tp.split + 95) / 96, ChainShape<P, H, false, 6>::NW * kWave, 0, st>>>(
+            net, n, x, u, zin, (S*)stash, y, amax, hsave, tp.split, n);
+        e = hipGetLastError();
+      }
+    }
+    return e;
   }
 }
 
@@ -780,29 +820,22 @@ hipError_t chain_reverse_v(const ChainCfg& cfg, const NetView& net, int n, const
     return hipErrorInvalidValue;
   } else {
     using S = typename StashT<P>::type;
-    const int nrows = 6 * n, nblk = (nrows + Sh::R - 1) / Sh::R;
-    const int grid = chain_grid(nblk, cfg);
+    const int nrows = 6 * n;
+    const int grid = chain_grid((nrows + Sh::R - 1) / Sh::R, cfg);
     if (grid <= 0) return hipSuccess;
-    int split = nrows;  // rows of this shape's launch; the rest go to the tail launch
-    int grid_main = grid;
-    if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) {
-      // a last round of 128-row blocks that would keep at most half of the
-      // resident workgroups busy (one per CU in this shape) runs instead as
-      // 64-row blocks spread over all of them
-      const int slots = grid < num_cu() ? grid : num_cu();
-      const int rem = nblk % slots;
-      if (nblk > slots && rem > 0 && 2 * rem <= slots) {
-        split = (nblk - rem) * Sh::R;
-        grid_main = chain_grid(nblk - rem, cfg);
-      }
-    }
-    mlp_reverse_chain<P, H, V><<<grid_main, Sh::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, 0, split);
+    TailPlan tp{nrows, 0, grid};
+    if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) tp = tail_plan(nrows, grid, cfg);
+    mlp_reverse_chain<P, H, V><<<tp.grid_main, Sh::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, 0,
+                                                                        tp.split);
     hipError_t e = hipGetLastError();
     if constexpr (V == 4 && ChainShape<P, H, true, 5>::VALID) {
-      if (e == hipSuccess && split < nrows) {
-        using S5 = ChainShape<P, H, true, 5>;
-        const int nb5 = (nrows - split + S5::R - 1) / S5::R;
-        mlp_reverse_chain<P, H, 5><<<nb5, S5::NW * kWave, 0, st>>>(net, n, (const S*)stash, J, amax, split, nrows);
+      if (e == hipSuccess && tp.tail_rows == 64) {
+        mlp_reverse_chain<P, H, 5><<<(nrows - tp.split + 63) / 64, ChainShape<P, H, true, 5>::NW * kWave, 0, st>>>(
+            net, n, (const S*)stash, J, amax, tp.split, nrows);
+        e = hipGetLastError();
+      } else if (e == hipSuccess && tp.tail_rows == 96) {
+        mlp_reverse_chain<P, H, 6><<<(nrows - tp.split + 95) / 96, ChainShape<P, H, true, 6>::NW * kWave, 0, st>>>(
+            net, n, (const S*)stash, J, amax, tp.split, nrows);
         e = hipGetLastError();
       }
     }

@@ -388,8 +388,29 @@ def test_exact_linearisation_matches_oracle(torch, prec, tol):
 @pytest.mark.parametrize("prec,H,L,tol", [("fp32", 512, 2, 1e-5), ("bf16", 512, 3, 1e-2), ("bf16", 1024, 2, 1e-2),
                                           ("fp8", 512, 3, 5e-2), ("fp8", 1024, 2, 5e-2)])
 def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
+    # 733 nodes: ragged in every tile height (32, 64, 96) for both directions
+    check_tile_choices(torch, prec, H, L, tol, 733,
+                       [(0, 0, 0, 0, 0), (0, 1, 0, 1, 0), (0, 1, 1, 1, 1), (0, 0, 3, 1, 7), (0, 1, 5, 0, 2),
+                        (0, 0, 10000, 0, 10000), (0, 2, 0, 2, 0), (0, 2, 3, 2, 5), (0, 2, 10000, 2, 1),
+                        (0, 0, 0, 3, 0), (0, 2, 0, 3, 3), (0, 2, 0, 4, 0), (0, 0, 0, 4, 3), (0, 4, 0, 4, 0),
+                        (0, 4, 5, 0, 0), (0, 0, 0, 4, 8), (0, 4, 0, 4, 16), (0, 4, 4, 4, 13)])
+
+
+# Variant 4 hands a last round of 128-row blocks that leaves at most half of the
+# workgroups busy to 64-row blocks, at most three quarters to 96-row blocks, in a
+# second launch, whose first reverse row need not start a node.  850 nodes: the
+# forward's 7 blocks on 4 workgroups leave 3 (96-row tail), on 7 none; the
+# reverse's 40 blocks on 11 leave 7 (96-row tail from row 4224, a node start), on
+# 17 leave 6 (64-row tail from row 4352 = 6 * 725 + 2), on 7 leave 5 (96-row tail
+# from row 4480 = 6 * 746 + 4).
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_tail_launch_shapes_match_oracle(torch, prec):
+    check_tile_choices(torch, prec, 512, 3, 1e-2 if prec == "bf16" else 5e-2, 850,
+                       [(0, 4, 4, 4, 11), (0, 4, 4, 4, 17), (0, 4, 7, 4, 7)])
+
+
+def check_tile_choices(torch, prec, H, L, tol, n, choices):
     import paper_2203_07747_amd as rtn
-    n = 733  # ragged in every tile height (32, 64, 96) for both directions
     x, u = sample_nodes(n, seed=41)
     Ws, bs = xavier_params(L, H, seed=42)
     m = rtn.Model(Ws, bs)
@@ -401,10 +422,7 @@ def test_every_tile_variant_and_grid_matches_oracle(torch, prec, H, L, tol):
     sc = calibrate_scales(net, pack_input(xc, uc)) if prec == "fp8" else None
     xt, ut = torch.from_numpy(x).cuda(), torch.from_numpy(u).cuda()
     try:
-        for choice in [(0, 0, 0, 0, 0), (0, 1, 0, 1, 0), (0, 1, 1, 1, 1), (0, 0, 3, 1, 7), (0, 1, 5, 0, 2),
-                       (0, 0, 10000, 0, 10000), (0, 2, 0, 2, 0), (0, 2, 3, 2, 5), (0, 2, 10000, 2, 1),
-                       (0, 0, 0, 3, 0), (0, 2, 0, 3, 3), (0, 2, 0, 4, 0), (0, 0, 0, 4, 3), (0, 4, 0, 4, 0),
-                       (0, 4, 5, 0, 0), (0, 0, 0, 4, 8), (0, 4, 0, 4, 16)]:
+        for choice in choices:
             if (choice[3] in (3, 4) or choice[1] == 4) and (prec == "fp32" or H != 512):
                 continue
             print(f"[gpu] tile choice {choice} prec={prec} H={H} L={L} n={n}", flush=True)

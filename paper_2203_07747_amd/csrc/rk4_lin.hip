@@ -21,12 +21,14 @@ namespace rtn {
 // 64 nodes per workgroup: phase (1) of rk4_block then fills one wave.
 constexpr int kRk4Nodes = 64, kRk4Threads = 256;
 
-__global__ void __launch_bounds__(kRk4Threads)
+// three waves per SIMD (<= 168 registers): the tangent passes are latency bound
+__global__ void __launch_bounds__(kRk4Threads) __attribute__((amdgpu_waves_per_eu(3)))
 rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, const float* __restrict__ u,
                      const float* __restrict__ fD, const float* __restrict__ JD, float* __restrict__ xn,
                      float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status, int input) {
   __shared__ float sm[kRk4Nodes * kNodeStride];
   __shared__ float tr[kRk4Nodes * kTrajStride];
+  __shared__ __align__(16) float stg[rk4_stage_floats(kRk4Threads)];
   __shared__ int flags[kRk4Nodes];
   const int tid = threadIdx.x;
   const int node0 = blockIdx.x * kRk4Nodes;
@@ -42,7 +44,7 @@ rk4_linearize_kernel(int n, QuadConst P, float dt, const float* __restrict__ x, 
   for (int i = tid; i < nn * kDout * kDin; i += kRk4Threads)
     sm[(i / (kDout * kDin)) * kNodeStride + 23 + (i % (kDout * kDin))] =
         JD ? JD[(size_t)node0 * kDout * kDin + i] : 0.f;
-  rk4_block(sm, tr, flags, nn, node0, tid, kRk4Threads, P, dt, JD != nullptr, xn, A, B, status, input);
+  rk4_block(sm, tr, stg, flags, nn, node0, tid, kRk4Threads, P, dt, JD != nullptr, xn, A, B, status, input);
 }
 
 hipError_t launch_rk4_linearize(int n, const QuadConst& q, float dt, const float* x, const float* u, const float* fD,

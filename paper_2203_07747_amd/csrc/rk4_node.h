@@ -125,13 +125,29 @@ __device__ inline bool rk4_trajectory(const float* s, const QuadConst& P, const 
   return ok;
 }
 
+// LDS -> global copy of cnt floats by the nt threads of a block: whole 16-byte
+// words where the destination is 16-byte aligned (src is), then the rest.
+__device__ inline void copy_out(float* __restrict__ dst, const float* src, int cnt, int tid, int nt) {
+  int done = 0;
+  if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+    const int n4 = cnt >> 2;
+    for (int i = tid; i < n4; i += nt) reinterpret_cast<float4*>(dst)[i] = reinterpret_cast<const float4*>(src)[i];
+    done = n4 << 2;
+  }
+  for (int i = done + tid; i < cnt; i += nt) dst[i] = src[i];
+}
+
+// Staging floats of one pass of rk4_block's phase (2): A and B of nt / 16 nodes.
+constexpr int rk4_stage_floats(int nt) { return ((nt / 16) * kNx * kNx + 3) / 4 * 4 + (nt / 16) * kNx * kNu; }
+
 // Throughput form: RK4 step of the nn nodes staged in sm (node i at sm + i kNodeStride:
 // x 13 | u 4 | y 6 | J 84), nodes node0 .. node0 + nn - 1 of the batch, by a block
 // of nt threads (nt a multiple of 16; phase (2) takes nt / 16 nodes at a time).
 // Every thread of the block calls it (it holds barriers).  has_J: J holds the
 // network Jacobian (w.r.t. its inputs); tr: nn kTrajStride floats of LDS;
-// flags: nn ints of LDS.
-__device__ inline void rk4_block(float* sm, float* tr, int* flags, int nn, int node0, int tid, int nt,
+// flags: nn ints of LDS; stg: rk4_stage_floats(nt) floats of 16-byte aligned LDS,
+// where each pass assembles its nodes' A and B before they go out as contiguous runs.
+__device__ inline void rk4_block(float* sm, float* tr, float* stg, int* flags, int nn, int node0, int tid, int nt,
                                  const QuadConst& P, float dt, bool has_J, float* __restrict__ xn,
                                  float* __restrict__ A, float* __restrict__ B, uint8_t* __restrict__ status,
                                  int input) {
@@ -165,14 +181,23 @@ __device__ inline void rk4_block(float* sm, float* tr, int* flags, int nn, int n
   const float dt6 = dt / 6.f;
   const float cst[4] = {0.f, 0.5f, 0.5f, 1.f};
   const float wst[4] = {1.f, 2.f, 2.f, 1.f};
-  for (int ln = tid >> 4; ln < nn; ln += nt >> 4) {
+  const int per = nt >> 4, slot = tid >> 4;
+  float* stA = stg;                                 // [per][13][13]
+  float* stB = stg + (per * kNx * kNx + 3) / 4 * 4;  // [per][13][4]
+  // A's position columns are the identity (no stage derivative depends on the
+  // position) and the passes write only columns 3..12: fill them once
+  for (int i = tid; i < per * kNx * 3; i += nt) {
+    const int row = (i / 3) % kNx, col = i % 3;
+    stA[(i / (3 * kNx)) * kNx * kNx + row * kNx + col] = row == col ? 1.f : 0.f;
+  }
+  for (int base = 0; base < nn; base += per) {  // uniform trip count: the passes hold barriers
+    const int ln = base + slot;
     const float* s = sm + ln * kNodeStride;
     const float* uk = s + 13;
     const float* J = s + 23;
     const float* trn = tr + ln * kTrajStride;
-    const int node = node0 + ln;
     int bad = 0;
-    if (c < 14) {
+    if (ln < nn && c < 14) {
       // input lanes: the state-independent part of d F / d u_j (mixer torques and
       // the network's J_u e_j); the thrust direction is added per stage
       float fu[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -225,18 +250,18 @@ __device__ inline void rk4_block(float* sm, float* tr, int* flags, int nn, int n
         bad |= !isfinite(col[i]);
       }
       // column xcol of A or ucol of B (one store sequence for both kinds of lane)
-      float* dst = xcol >= 0 ? A + (size_t)node * kNx * kNx + xcol : B + (size_t)node * kNx * kNu + ucol;
+      float* dst = xcol >= 0 ? stA + slot * kNx * kNx + xcol : stB + slot * kNx * kNu + ucol;
       const int ld = xcol >= 0 ? kNx : kNu;
 #pragma unroll
       for (int i = 0; i < 13; ++i) dst[i * ld] = col[i];
       if (bad) atomicOr(&flags[ln], 2);
-    } else if (c == 15) {
-      float* Ab = A + (size_t)node * kNx * kNx;
-#pragma unroll
-      for (int i = 0; i < 13; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Ab[i * kNx + j] = (i == j) ? 1.f : 0.f;
     }
+    __syncthreads();
+    // the pass's nodes are consecutive: their A and B are contiguous in global memory
+    const int m = nn - base < per ? nn - base : per;
+    copy_out(A + (size_t)(node0 + base) * kNx * kNx, stA, m * kNx * kNx, tid, nt);
+    copy_out(B + (size_t)(node0 + base) * kNx * kNu, stB, m * kNx * kNu, tid, nt);
+    __syncthreads();
   }
   if (status) {  // uniform over the block
     __syncthreads();
